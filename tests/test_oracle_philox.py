@@ -1,0 +1,106 @@
+"""Pins of the oracle's noise generator.
+
+Philox4x32-10 is checked against an independent pure-Python implementation of
+the SC'11 description (Salmon, Moraes, Dror, Shaw) and, on the GPU machine, against
+rocRAND run as a black box (tests/test_gpu_rocrand_pin.py).  The Box-Muller
+normals are checked for their distribution.
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+
+MASK = 0xFFFFFFFF
+
+
+def philox_ref(ctr, key, rounds=10):
+    """Philox4x32 as described in the SC'11 paper, written with Python ints."""
+    m0, m1 = 0xD2511F53, 0xCD9E8D57
+    w0, w1 = 0x9E3779B9, 0xBB67AE85
+    x = [int(v) for v in ctr]
+    k = [int(v) for v in key]
+    for r in range(rounds):
+        if r:
+            k = [(k[0] + w0) & MASK, (k[1] + w1) & MASK]
+        p0 = m0 * x[0]
+        p1 = m1 * x[2]
+        x = [((p1 >> 32) ^ x[1] ^ k[0]) & MASK, p1 & MASK, ((p0 >> 32) ^ x[3] ^ k[1]) & MASK, p0 & MASK]
+    return x
+
+
+def test_philox_matches_independent_implementation():
+    rng = np.random.default_rng(0)
+    for _ in range(300):
+        ctr = rng.integers(0, 2 ** 32, size=4, dtype=np.uint64)
+        key = rng.integers(0, 2 ** 32, size=2, dtype=np.uint64)
+        got = oracle.philox(ctr.astype(np.uint32), key.astype(np.uint32))
+        assert list(map(int, got)) == philox_ref(ctr, key)
+    # edge words
+    for ctr in ([0, 0, 0, 0], [MASK] * 4, [1, 0, 0, 0]):
+        for key in ([0, 0], [MASK, MASK]):
+            assert list(map(int, oracle.philox(ctr, key))) == philox_ref(ctr, key)
+
+
+def test_noise_counter_layout():
+    """Counter = (node, step_lo, block, step_hi), key = (seed_lo, seed_hi)."""
+    seed = 0x0123456789ABCDEF
+    step = (7 << 32) + 5
+    for block in range(6):
+        got = oracle.noise_words(seed, 1234, step, block)
+        ref = philox_ref([1234, 5, block, 7], [seed & MASK, seed >> 32])
+        assert list(map(int, got)) == ref
+
+
+def test_philox_bits_uniform():
+    words = np.array([oracle.noise_words(1, n, 0, 0) for n in range(4000)], dtype=np.uint64).ravel()
+    bits = ((words[:, None] >> np.arange(32, dtype=np.uint64)) & 1).astype(float)
+    frac = bits.mean(axis=0)
+    se = 0.5 / np.sqrt(len(words))
+    assert np.all(np.abs(frac - 0.5) < 5 * se)
+    # avalanche: flipping one counter bit flips about half the output bits
+    flips = []
+    for n in range(500):
+        a = np.array(oracle.noise_words(3, n, 11, 2), dtype=np.uint64)
+        b = np.array(oracle.noise_words(3, n ^ 1, 11, 2), dtype=np.uint64)
+        flips.append(sum(bin(int(v)).count("1") for v in (a ^ b)))
+    assert abs(np.mean(flips) - 64) < 2.0
+
+
+@pytest.mark.parametrize("bits", [32, 24])
+def test_normals_distribution(bits):
+    rs = np.array([oracle.normals(9, n, 17, bits)[4:] for n in range(6000)])  # (6000, 23)
+    x = rs.ravel()
+    assert abs(x.mean()) < 5 / np.sqrt(x.size)
+    assert abs(x.var() - 1.0) < 5 * np.sqrt(2.0 / x.size)
+    assert stats.kstest(x, "norm").pvalue > 1e-4
+    # different moments are uncorrelated
+    c = np.corrcoef(rs.T)
+    off = c[~np.eye(23, dtype=bool)]
+    assert np.max(np.abs(off)) < 5 / np.sqrt(rs.shape[0])
+
+
+def test_normals_zero_for_conserved_and_keyed():
+    r = oracle.normals(1, 5, 6)
+    assert np.all(r[:4] == 0)
+    assert not np.array_equal(r, oracle.normals(2, 5, 6))
+    assert not np.array_equal(r, oracle.normals(1, 6, 6))
+    assert not np.array_equal(r, oracle.normals(1, 5, 7))
+    assert np.array_equal(r, oracle.normals(1, 5, 6))
+
+
+def test_box_muller_pairs_from_words():
+    """r_{4+4j}, r_{5+4j} come from words (x0, x1) of block j, r_{6+4j}, r_{7+4j}
+    from (x2, x3): radius sqrt(-2 ln U1), angle 2 pi U2 with U = (x + 1/2) 2^-32."""
+    seed, node, step = 77, 3, 4
+    r = oracle.normals(seed, node, step)
+    for j in range(6):
+        w = oracle.noise_words(seed, node, step, j).astype(float)
+        for p in range(2):
+            u1 = (w[2 * p] + 0.5) / 2 ** 32
+            u2 = (w[2 * p + 1] + 0.5) / 2 ** 32
+            rad = np.sqrt(-2 * np.log(u1))
+            k = 4 + 4 * j + 2 * p
+            assert abs(r[k] - rad * np.cos(2 * np.pi * u2)) < 1e-14
+            if k + 1 < 27:
+                assert abs(r[k + 1] - rad * np.sin(2 * np.pi * u2)) < 1e-14
