@@ -213,12 +213,13 @@ void oracle_noise_words(uint64_t seed, uint32_t node, int64_t step, uint32_t blo
     oracle_philox4x32_10(ctr, key, out);
 }
 
-/* Uniform on (0,1) from a 32-bit word.  bits = 32: (x + 1/2) 2^-32.  bits = 24:
- * the top 24 bits, ((x >> 8) + 1/2) 2^-24 (the single-precision variant).
- * Both are exact in double. */
+/* Uniform on (0,1) from a 32-bit word.  bits = 32: (x + 1/2) 2^-32.  bits = 23:
+ * the top 23 bits, ((x >> 9) + 1/2) 2^-23, the single-precision variant (the
+ * largest width for which every such value is exact in binary32).  Both are
+ * exact in double. */
 static double uniform_of(uint32_t x, int bits)
 {
-    if (bits == 24) return ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0);
+    if (bits == 23) return ((double)(x >> 9) + 0.5) * (1.0 / 8388608.0);
     return ((double)x + 0.5) * (1.0 / 4294967296.0);
 }
 
@@ -252,7 +253,7 @@ typedef struct {
     double rho0, tau, kbt;
     uint64_t seed;
     int32_t noise_rho;   /* 0 = local rho in Eqs. (2),(9); 1 = rho0 */
-    int32_t noise_bits;  /* 32 (double uniforms) or 24 (single-precision uniforms) */
+    int32_t noise_bits;  /* 32 (double uniforms) or 23 (single-precision uniforms) */
 } oracle_params;
 
 /* ----------------------------------------------------------------------- */

@@ -67,7 +67,7 @@ def test_philox_bits_uniform():
     assert abs(np.mean(flips) - 64) < 2.0
 
 
-@pytest.mark.parametrize("bits", [32, 24])
+@pytest.mark.parametrize("bits", [32, 23])
 def test_normals_distribution(bits):
     rs = np.array([oracle.normals(9, n, 17, bits)[4:] for n in range(6000)])  # (6000, 23)
     x = rs.ravel()
