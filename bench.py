@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused GMF-FLBM D3Q27 stream+collide step on one MI355X.
+
+Default workload: 256^3 periodic box, rho0 = 1, tau = 0.8, k_B T = 1e-4, seed 1,
+FP32 shifted populations in SoA layout, HIP-graph step loop: the bandwidth
+headline (two 1.8 GB population buffers, far larger than the 256 MB last-level
+cache).  The same JSON line also reports the plain FP64 single-replica form on
+the same box, the batched ensemble (32 x 32^3 + 16 x 48^3 + 16 x 64^3 replicas
+in one launch per step), and the FP64 CPU oracle timed on the host cores.
+
+A step is one pass of the whole fused step (pull, moments, relaxation, ghost
+filter, Philox noise, back-projection, write) over every node.  Inputs are
+resident in device memory before timing starts.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES_PER_NODE = {"fp32": 216, "fp64": 432}   # 27 loads + 27 stores per node update
+METRIC = "GLUPS & % HBM roofline, FP32-batched vs FP64-plain, at matched variance accuracy"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("gmf_kernels.hip", "gmf_device.hpp"):
+        with open(os.path.join(ROOT, "paper_2601_03806_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key: str, nodes: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = data.get(kernel_key)
+    if not ent or ent.get("source_hash") != kernel_source_hash() or ent.get("nodes") != nodes:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def time_context(ctx, stream, steps, warmup, torch):
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3   # seconds
+
+
+def run_gpu(args, torch, gmf, wl):
+    stream = torch.cuda.Stream()
+    out = {}
+    # FP32 shifted, bandwidth headline
+    w = wl.bandwidth_headline("fp32")
+    b = w.boxes[0]
+    spec = gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed)
+    with gmf.Context([spec], precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune) as ctx:
+        print(f"[bench] fp32 {w.name}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+        sec = time_context(ctx, stream, args.steps, args.warmup, torch)
+        st = ctx.stats()
+        out["fp32"] = {"seconds": sec, "nodes": spec.n, "steps": args.steps, "config": ctx.config(),
+                       "mass_drift_rel": abs(st["mass"] - spec.n * b.rho0) / (spec.n * b.rho0)}
+    torch.cuda.synchronize()
+    if not args.skip_extra:
+        # plain FP64, same box
+        w64 = wl.bandwidth_headline("fp64")
+        s64 = max(10, args.steps // 5)
+        with gmf.Context([spec], precision=gmf.FP64, stream=stream, tune=args.tune) as ctx:
+            print(f"[bench] fp64 {w64.name}: steps {s64}", file=sys.stderr, flush=True)
+            sec = time_context(ctx, stream, s64, max(2, args.warmup // 5), torch)
+            out["fp64"] = {"seconds": sec, "nodes": spec.n, "steps": s64, "config": ctx.config()}
+        torch.cuda.synchronize()
+        # batched ensemble
+        we = wl.ensemble()
+        specs = [gmf.ReplicaSpec(*bx.n, rho0=bx.rho0, tau=bx.tau, kbt=bx.kbt, seed=bx.seed) for bx in we.boxes]
+        se = max(20, args.steps)
+        with gmf.Context(specs, precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune) as ctx:
+            print(f"[bench] batched {we.name}: steps {se}", file=sys.stderr, flush=True)
+            sec = time_context(ctx, stream, se, args.warmup, torch)
+            out["batched"] = {"seconds": sec, "nodes": we.nodes, "steps": se, "config": ctx.config(),
+                              "workload": we.name}
+        torch.cuda.synchronize()
+    return out
+
+
+def cpu_baseline(target_seconds=12.0):
+    import oracle
+    L = 16
+    p = oracle.params(L, rho0=1.0, tau=1.0, kbt=1e-4, seed=1)
+    f = oracle.rest_state(p)
+    t0 = time.perf_counter()
+    oracle.run(p, f, 0, 5)
+    dt = time.perf_counter() - t0
+    steps = max(5, int(target_seconds / max(dt / 5, 1e-6)))
+    t0 = time.perf_counter()
+    oracle.run(p, f, 5, steps)
+    dt = time.perf_counter() - t0
+    glups = L ** 3 * steps / dt / 1e9
+    return {"value": glups, "unit": "GLUPS", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"16^3 FP64 GMF-FLBM (tau=1, kbt=1e-4, seed 1), {steps} steps ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--tune", type=int, default=0)
+    ap.add_argument("--skip-extra", action="store_true", help="only the FP32 headline (profiling runs)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (replicas and slabs would shard "
+              "over GPUs by independent contexts; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2601_03806_amd as gmf
+    from paper_2601_03806_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
+    gmf.lib()   # fail loudly if the HIP library is missing
+
+    res = run_gpu(args, torch, gmf, wl)
+    r32 = res["fp32"]
+    glups = r32["nodes"] * r32["steps"] / r32["seconds"] / 1e9
+    ms = r32["seconds"] / r32["steps"] * 1e3
+    kernel_s = r32["seconds"] / r32["steps"]   # step kernel duration per launch (graph replays)
+    achieved = BYTES_PER_NODE["fp32"] * r32["nodes"] / kernel_s / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(glups, 4),
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (equilibrium fluid at rest, rho0=1, Philox noise)",
+        "config": {"workload": "d3q27_256cube_fp32_tau0.8", "lattice": [256, 256, 256], "rho0": 1.0,
+                   "tau": 0.8, "kbt": 1e-4, "seed": 1, "precision": "fp32_shifted",
+                   "layout": "SoA A/B pull", "kernel_config": r32["config"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("step_fp32_256", r32["nodes"])},
+        "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+        "mass_drift_rel": r32["mass_drift_rel"],
+    }
+    if "fp64" in res:
+        r = res["fp64"]
+        g = r["nodes"] * r["steps"] / r["seconds"] / 1e9
+        gbs = BYTES_PER_NODE["fp64"] * g
+        line["fp64_plain"] = {"workload": "d3q27_256cube_fp64_tau0.8", "glups": round(g, 4),
+                              "ms_per_step": round(r["seconds"] / r["steps"] * 1e3, 5),
+                              "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                              "steps": r["steps"], "kernel_config": r["config"]}
+    if "batched" in res:
+        r = res["batched"]
+        g = r["nodes"] * r["steps"] / r["seconds"] / 1e9
+        gbs = BYTES_PER_NODE["fp32"] * g
+        line["fp32_batched"] = {"workload": r["workload"], "replicas": 64, "glups": round(g, 4),
+                                "ms_per_step": round(r["seconds"] / r["steps"] * 1e3, 5),
+                                "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                                "steps": r["steps"], "kernel_config": r["config"]}
+    if not args.no_cpu and int(os.environ.get("RANK", 0)) == 0:
+        print("[bench] oracle timing on the host", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * gmf.h -- C ABI of the MI355X (gfx950) library for the ghost-mode filtered
+ * fluctuating lattice Boltzmann method (GMF-FLBM) on the D3Q27 lattice
+ * (Lauricella, Montessori, Tiribocchi, Succi, arXiv:2601.03806).
+ *
+ * The library advances one or more independent periodic boxes ("replicas")
+ * with the fused stream+collide update of Sec. II, Eq. (10):
+ *
+ *   f_i(x + c_i, t + 1) = f^eq_i + (1 - omega) f^neq_i
+ *                         + w_i sum_{k=4..9}   e_ki phi_k   r_k / b_k
+ *                         + w_i sum_{k=10..26} e_ki phi^g_k r_k / b_k
+ *
+ * with the second-order equilibrium (Eq. (11)), the filtered non-equilibrium
+ * part rebuilt from its second-order Hermite coefficient (Eqs. (12)-(13)),
+ * omega = 1/tau (Sec. II), and the noise amplitudes of Eqs. (2) and (9).
+ * The BGK-FLBM update of Eq. (1) is available as an option.
+ *
+ * Conventions (the paper leaves them open; the test oracle uses the same):
+ *   - Velocity order i = 0..26 (Table I groups): rest; faces +x,-x,+y,-y,+z,-z;
+ *     the 12 edges, then the 8 corners, each in lexicographic order of
+ *     (cx, cy, cz) with -1 < 0 < +1.
+ *   - Moment order k = 0..26 as printed in Table II.
+ *   - Node index n = x + nx*(y + ny*z); host population arrays are FP64,
+ *     laid out f[i*N + n] (N = nx*ny*nz) and hold the pre-collision state
+ *     f(x, t), i.e. the left-hand side of Eq. (10) after streaming.
+ *   - The collision that produces f(., t+1) from f(., t) has step index t.
+ *   - The standard normals r_k come from Philox4x32-10 (Salmon et al., SC'11),
+ *     key = (seed & 0xffffffff, seed >> 32), counter =
+ *     (n, t & 0xffffffff, j, t >> 32) for blocks j = 0..5; block j feeds
+ *     r_{4+4j} .. r_{7+4j} through the Box-Muller transform on the word pairs
+ *     (x0, x1) and (x2, x3): radius sqrt(-2 ln U1), angle 2 pi U2.  FP64 uses
+ *     U = (x + 1/2) 2^-32; FP32 uses U = ((x >> 9) + 1/2) 2^-23 (exact in binary32).
+ *   - Initial state: rest equilibrium f_i = w_i rho0 in every replica.
+ *
+ * Threading and synchronisation: a context is not thread-safe; distinct
+ * contexts are independent.  gmf_step only enqueues work on the context's
+ * stream; every other call that returns data synchronises that stream.
+ * No C++ exception crosses this interface; every function returns one of the
+ * GMF_* codes below.  After a HIP error a context is poisoned: every later
+ * call on it returns GMF_EDEVICE.
+ */
+#ifndef GMF_H
+#define GMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GMF_ABI_VERSION 1
+
+/* return codes */
+#define GMF_OK 0
+#define GMF_EINVAL (-1)     /* an argument is out of range (see each call)  */
+#define GMF_ENOMEM (-2)     /* device or host allocation failed             */
+#define GMF_EDEVICE (-3)    /* a HIP call failed; the context is poisoned   */
+#define GMF_ESTATE (-4)     /* NULL context                                 */
+#define GMF_EUNSTABLE (-5)  /* a sampled density was NaN or infinite       */
+
+/* gmf_options.precision */
+#define GMF_FP64 0          /* populations f stored and stepped in FP64     */
+#define GMF_FP32_SHIFTED 1  /* g = f - w rho0 stored and stepped in FP32    */
+/* gmf_options.collision */
+#define GMF_COLLISION_GMF 0 /* Eq. (10): ghost-mode filtered               */
+#define GMF_COLLISION_BGK 1 /* Eq. (1): BGK-FLBM, noise on k = 4..26 with omega(2-omega) */
+
+/* observables accumulated by the sampler (index into gmf_stats_t arrays) */
+#define GMF_NOBS 10
+#define GMF_OBS_DRHO 0      /* rho - rho0, rho of Eq. (3)                   */
+#define GMF_OBS_JX 1        /* rho u_x, Eq. (4)                             */
+#define GMF_OBS_JY 2
+#define GMF_OBS_JZ 3
+#define GMF_OBS_JSUM 4      /* sum_a rho u_a                                */
+#define GMF_OBS_PDIAG 5     /* sum_a (Pi_aa - rho0 cs^2), Pi = sum_i f_i c_i c_i */
+#define GMF_OBS_POFF 6      /* sum_{a<b} Pi_ab                              */
+#define GMF_OBS_UX 7        /* u_x = j_x / rho                              */
+#define GMF_OBS_UY 8
+#define GMF_OBS_UZ 9
+/* shell spectra S_m(|k|) (Results section), normalised DFT
+ * m(k) = N^-1/2 sum_x m(x) exp(-i k.x), k_a = 2 pi n_a / L_a, averaged over all
+ * integer vectors n of the shell |n|^2 = 1,2,3,4,5,6,8,9 */
+#define GMF_NSPEC 5
+#define GMF_SPEC_RHO 0
+#define GMF_SPEC_J 1        /* mean over the three components of j          */
+#define GMF_SPEC_JSUM 2
+#define GMF_SPEC_PDIAG 3
+#define GMF_SPEC_POFF 4
+#define GMF_NSHELL 8
+
+typedef struct gmf_ctx gmf_ctx;   /* opaque, owned by the library */
+
+/* One periodic box.  Lattice size and periodic box, rho0 ("rho = 1" in the
+ * Results section), tau = 1/omega (Sec. II), k_B T (Eqs. (2), (9)), seed of
+ * the noise stream. */
+typedef struct {
+    int32_t nx, ny, nz;   /* >= 1 each; nx*ny*nz < 2^31                     */
+    int32_t reserved;     /* must be 0                                      */
+    double rho0;          /* > 0                                            */
+    double tau;           /* > 0.5                                          */
+    double kbt;           /* >= 0; 0 switches the noise off                 */
+    uint64_t seed;        /* Philox key                                     */
+} gmf_replica;
+
+typedef struct {
+    int32_t precision;    /* GMF_FP64 or GMF_FP32_SHIFTED                   */
+    int32_t collision;    /* GMF_COLLISION_GMF or GMF_COLLISION_BGK         */
+    int32_t noise_rho;    /* 0: local rho in Eqs. (2)/(9); 1: rho0         */
+    int32_t sample_every; /* > 0: sample f(., t) at every step with t % sample_every == 0; 0: off */
+    int32_t graph_steps;  /* steps per captured HIP graph; 0: direct launches; < 0: default (64) */
+    int32_t tune;         /* 0: built-in kernel configuration; 1: time the variants at init */
+    int32_t reserved[2];  /* must be 0                                      */
+} gmf_options;
+
+typedef struct {
+    int64_t step;                           /* current step index t         */
+    int64_t nsamples;                       /* samples accumulated          */
+    int64_t nonfinite;                      /* non-finite densities seen    */
+    double mass;                            /* sum_x rho(x, t), FP64        */
+    double momentum[3];                     /* sum_x rho u(x, t), FP64      */
+    double sum_mean[GMF_NOBS];              /* sum over samples of the spatial mean          */
+    double sum_meansq[GMF_NOBS];            /* sum over samples of the spatial mean of o^2   */
+    double sum_var[GMF_NOBS];               /* sum over samples of the spatial variance      */
+    double spectrum[GMF_NSPEC][GMF_NSHELL]; /* sum over samples of the shell average |m(k)|^2 */
+    int32_t shell_n2[GMF_NSHELL];           /* |n|^2 of each shell          */
+    int32_t shell_count[GMF_NSHELL];        /* integer vectors per shell    */
+} gmf_stats_t;
+
+/* Device bytes gmf_init needs when the caller provides the workspace.
+ * Returns 0 when the arguments are invalid. */
+size_t gmf_workspace_bytes(const gmf_replica* reps, int32_t nrep, const gmf_options* opt);
+
+/* Create a context for nrep replicas and set each to rest equilibrium.
+ *   reps, opt       host pointers, read during the call only (opt may be NULL
+ *                   for the defaults: FP64, GMF, local rho, no sampling).
+ *   dev_workspace   device pointer of at least ws_bytes >= gmf_workspace_bytes
+ *                   bytes, caller-owned, must outlive the context; NULL lets
+ *                   the library allocate (and free at gmf_destroy).
+ *   hip_stream      hipStream_t to enqueue on (caller-owned, must outlive the
+ *                   context and must not be the legacy NULL stream when
+ *                   graph_steps != 0); NULL: the library creates its own.
+ * Errors: GMF_EINVAL for any out-of-range field (including a workspace that is
+ * too small or misaligned to 256 bytes), GMF_ENOMEM, GMF_EDEVICE. */
+int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt,
+             void* dev_workspace, size_t ws_bytes, void* hip_stream, gmf_ctx** out);
+
+/* Enqueue n >= 0 steps of Eq. (10) (or Eq. (1)) on every replica.  Asynchronous. */
+int gmf_step(gmf_ctx* ctx, int64_t n);
+
+/* Density rho (N values) and velocity u = j/rho (3N values, ux | uy | uz) of
+ * the current state of replica r, Eqs. (3)-(4), into caller-owned host
+ * buffers (either may be NULL).  Synchronises. */
+int gmf_moments(gmf_ctx* ctx, int32_t r, double* rho, double* u);
+
+/* Statistics of replica r: current FP64 mass and momentum, and the sums of the
+ * sampled observables (see gmf_stats_t).  Synchronises.  Returns
+ * GMF_EUNSTABLE (after filling *out) when a sampled density was not finite. */
+int gmf_stats(gmf_ctx* ctx, int32_t r, gmf_stats_t* out);
+
+/* Zero the sample accumulators of every replica. */
+int gmf_reset_stats(gmf_ctx* ctx);
+
+/* Canonical populations f(x, t) of replica r (27*N FP64 values, host). */
+int gmf_get_populations(gmf_ctx* ctx, int32_t r, double* f);
+/* Overwrite the state of replica r with f(x, t) (27*N FP64 values, host). */
+int gmf_set_populations(gmf_ctx* ctx, int32_t r, const double* f);
+/* Canonical populations at `count` listed nodes (node indices 0 <= n < N, host
+ * array) of replica r into f[27*j + i] (host).  Synchronises. */
+int gmf_get_nodes(gmf_ctx* ctx, int32_t r, const int64_t* nodes, int32_t count, double* f);
+
+/* Current step index t. */
+int gmf_get_step(gmf_ctx* ctx, int64_t* t);
+
+/* Run the device noise generator that the step kernels use for `count`
+ * consecutive nodes node0.. at step t: words[24*j + 4*b + q] is word q of
+ * Philox block b for node node0+j; normals[23*j + (k-4)] is r_k, k = 4..26.
+ * precision selects the FP64 or FP32 normal transform (FP32 results are
+ * widened to double).  Host output arrays; either may be NULL.  Uses a
+ * private stream and synchronises. */
+int gmf_noise_probe(uint64_t seed, int64_t t, uint32_t node0, int32_t count, int32_t precision,
+                    uint32_t* words, double* normals);
+
+/* Kernel configuration in use (for reports): nodes per thread, threads per
+ * block, and 1 if the step loop runs through HIP graphs. */
+int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int32_t* graphs);
+
+/* Release the context and everything the library allocated for it. */
+void gmf_destroy(gmf_ctx* ctx);
+
+/* Static description of a return code. */
+const char* gmf_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMF_H */

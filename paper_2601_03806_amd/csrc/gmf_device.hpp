@@ -1,0 +1,167 @@
+// gmf_device.hpp -- device-side building blocks of the GMF-FLBM step on gfx950:
+// lattice constants in the library's internal population order, the per-replica
+// parameter record, fast integer division, Philox4x32-10 and the normal
+// transforms.
+//
+// Internal population order ("tensor order"): p = 9 (cx+1) + 3 (cy+1) + (cz+1)
+// for c = (cx, cy, cz) in {-1,0,1}^3.  With this order the D3Q27 weights and the
+// full-Hermite basis of Table II factorise over the three axes, which is what
+// the separable moment transforms in the step kernel use.  The host interface
+// converts to and from the documented canonical order (see gmf.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gmf {
+
+constexpr int Q = 27;
+constexpr int kBlock = 256;          // threads per workgroup of the lattice kernels
+constexpr int kObs = 10;             // sampled observables (see gmf.h)
+constexpr int kPartialStride = 24;   // doubles per workgroup partial record (2*kObs + 1, padded)
+constexpr int kFields = 6;           // fields kept for the spectra: drho, jx, jy, jz, pdiag, poff
+constexpr int kDftNx = 4;            // n_x = 0..3 in the first DFT stage
+constexpr int kDftNy = 7;            // n_y = -3..3
+constexpr int kDftPlane = kDftNx * kDftNy;
+constexpr int kShells = 8;
+constexpr int kSpec = 5;
+constexpr int kAccStride = 3 * kObs + kSpec * kShells + 8;  // doubles per replica accumulator
+
+__host__ __device__ constexpr int tcx(int p) { return p / 9 - 1; }
+__host__ __device__ constexpr int tcy(int p) { return (p / 3) % 3 - 1; }
+__host__ __device__ constexpr int tcz(int p) { return p % 3 - 1; }
+__host__ __device__ constexpr int tindex(int cx, int cy, int cz) { return 9 * (cx + 1) + 3 * (cy + 1) + (cz + 1); }
+
+// D1Q3 weight factor: w(c) = w1(cx) w1(cy) w1(cz), w1(0) = 2/3, w1(+-1) = 1/6
+__host__ __device__ constexpr double w1(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+__host__ __device__ constexpr double tweight(int p) { return w1(tcx(p)) * w1(tcy(p)) * w1(tcz(p)); }
+
+// Round-up magic-number division for 0 <= n < 2^31 and 1 <= d < 2^31
+// (Granlund & Montgomery, PLDI'94): q = (mulhi(n, m) + n) >> s with
+// s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1.
+struct FastDiv {
+    uint32_t d, m, s;
+};
+
+inline FastDiv make_fastdiv(uint32_t d)
+{
+    uint32_t s = 0;
+    while ((1ull << s) < d) ++s;
+    uint64_t m = ((((1ull << s) - d) << 32) / d) + 1;
+    return FastDiv{d, (uint32_t)m, s};
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f)
+{
+    return (__umulhi(n, f.m) + n) >> f.s;
+}
+
+// Per-replica record read by every lattice kernel (uniform across a workgroup).
+struct RepDev {
+    uint64_t pop_offset;      // element offset of the replica's 27*N block in a population buffer
+    uint64_t field_offset;    // element offset of the replica's kFields*N block in the field buffer
+    uint32_t nx, ny, nz, n;   // box and node count
+    FastDiv divx, divy;
+    uint32_t block_begin;     // first workgroup of this replica in the lattice grid
+    uint32_t nblocks;         // workgroups of this replica in the lattice grid
+    uint32_t key0, key1;      // Philox key
+    uint32_t dft_offset;      // offset (in complex values) of the replica's DFT partials
+    uint32_t noise_on;        // 0 when k_BT = 0
+    uint32_t noise_rho0;      // 1: rho0 instead of the local rho in the noise amplitudes
+    uint32_t pad0;
+    double rho0;
+    double omega;             // 1 / tau
+    double one_m_omega;       // 1 - omega
+    double amp[8];            // noise amplitudes / sqrt(rho): groups of equal b_k (see host)
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10: ten rounds of two 32x32->64 multiplies and xors, key bumped by
+// the Weyl constants between rounds (Salmon et al., SC'11).
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        U4 o;
+        o.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+        o.y = (uint32_t)p1;
+        o.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        o.w = (uint32_t)p0;
+        c = o;
+    }
+    return c;
+}
+
+// Block j of the noise of node n at step t.
+__device__ __forceinline__ U4 noise_block(uint32_t n, uint64_t t, uint32_t j, uint32_t k0, uint32_t k1)
+{
+    return philox4x32_10(U4{n, (uint32_t)t, j, (uint32_t)(t >> 32)}, k0, k1);
+}
+
+// Box-Muller pair from two words.
+template <typename T>
+struct Normal;
+
+template <>
+struct Normal<double> {
+    __device__ __forceinline__ static void pair(uint32_t a, uint32_t b, double& r0, double& r1)
+    {
+        const double u1 = ((double)a + 0.5) * 0x1p-32;
+        const double u2 = ((double)b + 0.5) * 0x1p-32;
+        const double rad = sqrt(-2.0 * log(u1));
+        double s, c;
+        sincospi(2.0 * u2, &s, &c);
+        r0 = rad * c;
+        r1 = rad * s;
+    }
+};
+
+template <>
+struct Normal<float> {
+    __device__ __forceinline__ static void pair(uint32_t a, uint32_t b, float& r0, float& r1)
+    {
+        // top 23 bits: (m + 1/2) 2^-23 is exact in binary32
+        const float u1 = __builtin_fmaf((float)(a >> 9), 0x1p-23f, 0x1p-24f);
+        const float u2 = __builtin_fmaf((float)(b >> 9), 0x1p-23f, 0x1p-24f);
+        // -2 ln u1 = -2 ln(2) log2(u1); v_log_f32 is log2, v_sin/v_cos take revolutions
+        const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+        r0 = rad * __builtin_amdgcn_cosf(u2);
+        r1 = rad * __builtin_amdgcn_sinf(u2);
+    }
+};
+
+// The 23 standard normals r_4..r_26 of one node and step, r[k-4].
+template <typename T>
+__device__ __forceinline__ void node_normals(uint32_t n, uint64_t t, uint32_t k0, uint32_t k1, T r[23])
+{
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const U4 w = noise_block(n, t, (uint32_t)j, k0, k1);
+        T a, b, c, d;
+        Normal<T>::pair(w.x, w.y, a, b);
+        r[4 * j + 0] = a;
+        r[4 * j + 1] = b;
+        if (j < 5) {
+            Normal<T>::pair(w.z, w.w, c, d);
+            r[4 * j + 2] = c;
+            r[4 * j + 3] = d;
+        } else {
+            // k = 26 is the last mode; the sine of the last pair is unused
+            Normal<T>::pair(w.z, w.w, c, d);
+            r[22] = c;
+        }
+    }
+}
+
+}  // namespace gmf

@@ -1,0 +1,65 @@
+// gmf_internal.hpp -- interface between the host runtime (gmf_runtime.cpp) and
+// the kernels (gmf_kernels.hip).  Not installed, not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gmf_device.hpp"
+
+namespace gmf {
+
+enum Precision { kFP64 = 0, kFP32Shifted = 1 };
+enum Collision { kGMF = 0, kBGK = 1 };
+
+// accumulator record of one replica (doubles)
+constexpr int kAccNsamp = 0;
+constexpr int kAccNonfinite = 1;
+constexpr int kAccMean = 2;
+constexpr int kAccMeanSq = kAccMean + kObs;
+constexpr int kAccVar = kAccMeanSq + kObs;
+constexpr int kAccSpec = kAccVar + kObs;
+static_assert(kAccSpec + kSpec * kShells <= kAccStride, "accumulator record too small");
+
+struct StepArgs {
+    const void* src;              // population buffer read at this step
+    void* dst;                    // population buffer written at this step
+    const RepDev* reps;
+    const uint16_t* blk2rep;      // workgroup -> replica (NULL when nrep == 1)
+    const int64_t* d_step;        // device step counter (NULL: step_base is the step)
+    int64_t step_base;            // step = step_base + (d_step ? *d_step : 0)
+    void* fields;                 // sampled fields (SAMPLE variants)
+    double* partials;             // per-workgroup partial sums (SAMPLE variants)
+};
+
+// lattice kernels
+hipError_t launch_step(int precision, int collision, bool sample, int npt, const StepArgs& a,
+                       uint32_t nblocks, hipStream_t s);
+hipError_t launch_init(int precision, void* buf, const RepDev* rep_dev, const RepDev& rep, hipStream_t s);
+hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* partials, double* acc,
+                               hipStream_t s);
+hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint16_t* plane2rep,
+                      uint32_t nplanes, const void* fields, double* dft, double* acc, int max_nx, int max_ny,
+                      hipStream_t s);
+hipError_t launch_set_step(int64_t* d_step, int64_t value, hipStream_t s);
+hipError_t launch_advance_step(int64_t* d_step, int64_t by, hipStream_t s);
+
+// host-interface helpers (chunks of z planes of one replica)
+hipError_t launch_gather(int precision, const void* src, const RepDev* rep_dev, const RepDev& rep,
+                         uint32_t z0, uint32_t z1, double* out, hipStream_t s);
+hipError_t launch_scatter(int precision, void* dst, const RepDev* rep_dev, const RepDev& rep,
+                          uint32_t z0, uint32_t z1, const double* in, hipStream_t s);
+hipError_t launch_moments(int precision, const void* src, const RepDev* rep_dev, const RepDev& rep,
+                          uint32_t z0, uint32_t z1, double* rho, double* u, double* partials,
+                          hipStream_t s);
+hipError_t launch_sum_partials(const double* partials, uint32_t nblocks, double* out4, int accumulate,
+                               hipStream_t s);
+hipError_t launch_nodes(int precision, const void* src, const RepDev* rep_dev, const int64_t* nodes,
+                        int32_t count, double* out, hipStream_t s);
+hipError_t launch_noise_probe(int precision, uint64_t seed, int64_t t, uint32_t node0, int32_t count,
+                              uint32_t* words, double* normals, hipStream_t s);
+
+// canonical velocity order of the interface -> internal tensor order
+void canonical_to_tensor(int out[Q]);
+
+}  // namespace gmf

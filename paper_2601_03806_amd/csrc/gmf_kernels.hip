@@ -1,0 +1,832 @@
+// gmf_kernels.hip -- gfx950 kernels of the GMF-FLBM library.
+//
+// The step kernel fuses, per lattice node (Sec. II):
+//   pull of the 27 populations from the neighbours (periodic box),
+//   the ten hydrodynamic moments rho, j, Pi (Eqs. (3), (4), (13)),
+//   the second-order equilibrium and the relaxation of the stress by
+//   (1 - omega) (Eqs. (10)-(12)),
+//   the Philox4x32-10 normals and the noise amplitudes of Eqs. (2) and (9),
+//   the projection back to populations (Eq. (10)), and the write.
+// The ghost moments of f are never formed: Eq. (10) keeps none of their
+// deterministic content.  Moments and the back-projection are separable
+// 3-point transforms along x, y, z in the internal tensor order, because the
+// D3Q27 weights and the Table II basis factorise over the axes
+// (w_i = w1(cx) w1(cy) w1(cz), e_k = h_a(cx) h_b(cy) h_c(cz) with
+// h0 = 1, h1 = c, h2 = c^2 - 1/3).
+#include <hip/hip_runtime.h>
+
+#include "gmf_device.hpp"
+#include "gmf_internal.hpp"
+
+namespace gmf {
+
+// ---------------------------------------------------------------------------
+// Separable transforms
+// ---------------------------------------------------------------------------
+
+// One axis of the back-projection f*(c) = sum_abc T[cx][a] T[cy][b] T[cz][c] M_abc,
+// T[c][a] = w1(c) h_a(c) / |h_a|^2 with |h|^2 = (1, 1/3, 2/9):
+//   T[-1] = (1/6, -1/2, 1/2),  T[0] = (2/3, 0, -1),  T[+1] = (1/6, 1/2, 1/2).
+template <typename T>
+__device__ __forceinline__ void tr3(T a0, T a1, T a2, T& om, T& oz, T& op)
+{
+    const T s = a0 * T(1.0 / 6.0) + a2 * T(0.5);
+    const T h = a1 * T(0.5);
+    oz = a0 * T(2.0 / 3.0) - a2;
+    om = s - h;
+    op = s + h;
+}
+
+// M[9a + 3b + c] (Hermite coefficient of order (a,b,c)) -> F[p] (tensor order)
+template <typename T>
+__device__ __forceinline__ void back_project(const T M[Q], T F[Q])
+{
+    T N[Q], P[Q];
+#pragma unroll
+    for (int ab = 0; ab < 9; ++ab)
+        tr3(M[3 * ab + 0], M[3 * ab + 1], M[3 * ab + 2], N[3 * ab + 0], N[3 * ab + 1], N[3 * ab + 2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int cz = 0; cz < 3; ++cz)
+            tr3(N[9 * a + 0 + cz], N[9 * a + 3 + cz], N[9 * a + 6 + cz],
+                P[9 * a + 0 + cz], P[9 * a + 3 + cz], P[9 * a + 6 + cz]);
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+        tr3(P[q], P[9 + q], P[18 + q], F[q], F[9 + q], F[18 + q]);
+}
+
+// Raw moments of order <= 2: s0 = sum f, j = sum f c, pi = sum f c c.
+template <typename T>
+struct Hydro {
+    T s0, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
+};
+
+template <typename T>
+__device__ __forceinline__ Hydro<T> forward_moments(const T f[Q])
+{
+    T X0[9], X1[9], X2[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const T a = f[q], b = f[9 + q], c = f[18 + q];   // cx = -1, 0, +1
+        X2[q] = a + c;
+        X0[q] = X2[q] + b;
+        X1[q] = c - a;
+    }
+    T Y00[3], Y01[3], Y02[3], Y10[3], Y11[3], Y20[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {                      // cz index; cy lines q = 3*cyi + r
+        Y02[r] = X0[r] + X0[6 + r];
+        Y00[r] = Y02[r] + X0[3 + r];
+        Y01[r] = X0[6 + r] - X0[r];
+        Y10[r] = X1[r] + X1[3 + r] + X1[6 + r];
+        Y11[r] = X1[6 + r] - X1[r];
+        Y20[r] = X2[r] + X2[3 + r] + X2[6 + r];
+    }
+    Hydro<T> h;
+    h.pzz = Y00[0] + Y00[2];
+    h.s0 = h.pzz + Y00[1];
+    h.jz = Y00[2] - Y00[0];
+    h.jy = Y01[0] + Y01[1] + Y01[2];
+    h.pyz = Y01[2] - Y01[0];
+    h.pyy = Y02[0] + Y02[1] + Y02[2];
+    h.jx = Y10[0] + Y10[1] + Y10[2];
+    h.pxz = Y10[2] - Y10[0];
+    h.pxy = Y11[0] + Y11[1] + Y11[2];
+    h.pxx = Y20[0] + Y20[1] + Y20[2];
+    return h;
+}
+
+// (a,b,c) Hermite orders of the Table II ghost vectors k = 10..26, as 9a+3b+c
+__device__ constexpr int kGhostSlot[17] = {
+    21, 19, 15, 11, 7, 5,   // x^2y, x^2z, y^2x, z^2x, y^2z, z^2y
+    13,                     // xyz
+    24, 20, 8,              // x^2y^2, x^2z^2, y^2z^2
+    14, 16, 22,             // xyz^2, xzy^2, yzx^2
+    23, 25, 17,             // x^2yz^2, x^2zy^2, y^2xz^2
+    26};                    // x^2y^2z^2
+// amplitude group of each ghost (index into RepDev::amp)
+__device__ constexpr int kGhostGroup[17] = {2, 2, 2, 2, 2, 2, 3, 4, 4, 4, 5, 5, 5, 6, 6, 6, 7};
+
+// ---------------------------------------------------------------------------
+// The fused stream + collide step
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ const T* pop_ptr(const void* base, uint64_t off)
+{
+    return reinterpret_cast<const T*>(base) + off;
+}
+
+template <typename T>
+__device__ __forceinline__ T ldg(const T* base, uint32_t idx)
+{
+    // 32-bit byte offset from a uniform base: lets the backend use the
+    // scalar-base + vector-offset addressing form
+    const uint32_t boff = idx * (uint32_t)sizeof(T);
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+}
+
+template <typename T>
+__device__ __forceinline__ void stg(T* base, uint32_t idx, T v)
+{
+    const uint32_t boff = idx * (uint32_t)sizeof(T);
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
+}
+
+template <typename T, bool SHIFTED, int COLL, bool SAMPLE>
+__device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, uint32_t n, uint64_t t,
+                                            double* acc)
+{
+    const uint32_t nx = R.nx, ny = R.ny, nz = R.nz, N = R.n;
+    const uint32_t yz = fdiv(n, R.divx);
+    const uint32_t x = n - yz * nx;
+    const uint32_t z = fdiv(yz, R.divy);
+    const uint32_t y = yz - z * ny;
+    const uint32_t plane = nx * ny;
+
+    // pull: f_p(x) = f*_p(x - c_p); index 0/1/2 <-> c = -1/0/+1
+    uint32_t xs[3], ys[3], zs[3];
+    xs[0] = (x + 1 == nx) ? 0u : x + 1;
+    xs[1] = x;
+    xs[2] = (x == 0) ? nx - 1 : x - 1;
+    const uint32_t yp = (y + 1 == ny) ? 0u : y + 1, ym = (y == 0) ? ny - 1 : y - 1;
+    const uint32_t zp = (z + 1 == nz) ? 0u : z + 1, zm = (z == 0) ? nz - 1 : z - 1;
+    ys[0] = yp * nx; ys[1] = y * nx; ys[2] = ym * nx;
+    zs[0] = zp * plane; zs[1] = z * plane; zs[2] = zm * plane;
+
+    const T* src = pop_ptr<T>(a.src, R.pop_offset);
+    T f[Q];
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const uint32_t idx = zs[p % 3] + ys[(p / 3) % 3] + xs[p / 9];
+        f[p] = ldg(src + (uint64_t)p * N, idx);
+    }
+
+    // noise words do not depend on the populations: issue them while the loads fly
+    T r[23];
+    if (R.noise_on) node_normals<T>(n, t, R.key0, R.key1, r);
+
+    const Hydro<T> h = forward_moments(f);
+    const T rho0 = (T)R.rho0;
+    const T rho = SHIFTED ? rho0 + h.s0 : h.s0;
+    const T irho = T(1) / rho;
+    const T cs2 = T(1.0 / 3.0);
+    const T om = (T)R.omega, omm = (T)R.one_m_omega;
+
+    // equilibrium second-order Hermite coefficient rho u u = j j / rho
+    const T exx = h.jx * h.jx * irho, eyy = h.jy * h.jy * irho, ezz = h.jz * h.jz * irho;
+    const T exy = h.jx * h.jy * irho, exz = h.jx * h.jz * irho, eyz = h.jy * h.jz * irho;
+
+    T M[Q];
+    if (COLL == kGMF) {
+        // Hermite coefficient of f: a2 = Pi - rho cs2 I (shifted: the rho0 parts cancel)
+        const T a2xx = h.pxx - cs2 * h.s0, a2yy = h.pyy - cs2 * h.s0, a2zz = h.pzz - cs2 * h.s0;
+        M[0] = h.s0;
+        M[9] = h.jx; M[3] = h.jy; M[1] = h.jz;
+        M[18] = om * exx + omm * a2xx;
+        M[6] = om * eyy + omm * a2yy;
+        M[2] = om * ezz + omm * a2zz;
+        M[12] = om * exy + omm * h.pxy;
+        M[10] = om * exz + omm * h.pxz;
+        M[4] = om * eyz + omm * h.pyz;
+    } else {
+        // BGK: f* = (1 - omega) f + omega f^eq + noise; f^eq has moments (rho, j, rho uu)
+        M[0] = om * h.s0;
+        M[9] = om * h.jx; M[3] = om * h.jy; M[1] = om * h.jz;
+        M[18] = om * exx; M[6] = om * eyy; M[2] = om * ezz;
+        M[12] = om * exy; M[10] = om * exz; M[4] = om * eyz;
+    }
+#pragma unroll
+    for (int g = 0; g < 17; ++g) M[kGhostSlot[g]] = T(0);
+
+    if (R.noise_on) {
+        // density in Eqs. (2), (9): local rho, or rho0 when the replica asks for it
+        const T sr = sqrt(R.noise_rho0 ? rho0 : rho);
+        const T sh0 = (T)R.amp[0] * sr, sh1 = (T)R.amp[1] * sr;
+        M[18] += sh0 * r[0]; M[6] += sh0 * r[1]; M[2] += sh0 * r[2];
+        M[12] += sh1 * r[3]; M[10] += sh1 * r[4]; M[4] += sh1 * r[5];
+#pragma unroll
+        for (int g = 0; g < 17; ++g) M[kGhostSlot[g]] = ((T)R.amp[kGhostGroup[g]] * sr) * r[6 + g];
+    }
+
+    T F[Q];
+    back_project(M, F);
+    if (COLL == kBGK) {
+#pragma unroll
+        for (int p = 0; p < Q; ++p) F[p] += omm * f[p];
+    }
+
+    T* dst = reinterpret_cast<T*>(a.dst) + R.pop_offset;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) stg(dst + (uint64_t)p * N, n, F[p]);
+
+    if (SAMPLE) {
+        const T drho = SHIFTED ? h.s0 : h.s0 - rho0;
+        const T pdiag = SHIFTED ? (h.pxx + h.pyy + h.pzz) : (h.pxx + h.pyy + h.pzz - T(3) * cs2 * rho0);
+        const T poff = h.pxy + h.pxz + h.pyz;
+        T* fl = reinterpret_cast<T*>(a.fields) + R.field_offset;
+        stg(fl + 0ull * N, n, drho);
+        stg(fl + 1ull * N, n, h.jx);
+        stg(fl + 2ull * N, n, h.jy);
+        stg(fl + 3ull * N, n, h.jz);
+        stg(fl + 4ull * N, n, pdiag);
+        stg(fl + 5ull * N, n, poff);
+        double o[kObs];
+        o[0] = (double)drho;
+        o[1] = (double)h.jx; o[2] = (double)h.jy; o[3] = (double)h.jz;
+        o[4] = (double)h.jx + (double)h.jy + (double)h.jz;
+        o[5] = (double)pdiag;
+        o[6] = (double)poff;
+        o[7] = (double)(h.jx * irho); o[8] = (double)(h.jy * irho); o[9] = (double)(h.jz * irho);
+#pragma unroll
+        for (int q = 0; q < kObs; ++q) {
+            acc[2 * q] += o[q];
+            acc[2 * q + 1] += o[q] * o[q];
+        }
+        acc[2 * kObs] += isfinite(o[0]) ? 0.0 : 1.0;
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], double* out)
+{
+    __shared__ double red[kBlock / 64][NV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        v[q] = s;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) red[wave][q] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int NPT>
+__global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a)
+{
+    const uint32_t blk = blockIdx.x;
+    const int r = a.blk2rep ? (int)a.blk2rep[blk] : 0;
+    const RepDev& R = a.reps[r];
+    const uint64_t t = (uint64_t)(a.step_base + (a.d_step ? *a.d_step : 0));
+    const uint32_t base = (blk - R.block_begin) * (uint32_t)(kBlock * NPT) + threadIdx.x;
+    double acc[2 * kObs + 1];
+    if (SAMPLE) {
+#pragma unroll
+        for (int q = 0; q < 2 * kObs + 1; ++q) acc[q] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const uint32_t n = base + (uint32_t)(k * kBlock);
+        if (n < R.n) node_update<T, SHIFTED, COLL, SAMPLE>(a, R, n, t, acc);
+    }
+    if (SAMPLE) block_sum_store<2 * kObs + 1>(acc, a.partials + (size_t)blk * kPartialStride);
+}
+
+template <typename T, bool SHIFTED, int COLL, bool SAMPLE>
+static hipError_t launch_step_npt(int npt, const StepArgs& a, uint32_t nblocks, hipStream_t s)
+{
+    switch (npt) {
+    case 1: step_kernel<T, SHIFTED, COLL, SAMPLE, 1><<<nblocks, kBlock, 0, s>>>(a); break;
+    case 2: step_kernel<T, SHIFTED, COLL, SAMPLE, 2><<<nblocks, kBlock, 0, s>>>(a); break;
+    case 4: step_kernel<T, SHIFTED, COLL, SAMPLE, 4><<<nblocks, kBlock, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, bool SHIFTED>
+static hipError_t launch_step_t(int collision, bool sample, int npt, const StepArgs& a, uint32_t nb, hipStream_t s)
+{
+    if (collision == kGMF)
+        return sample ? launch_step_npt<T, SHIFTED, kGMF, true>(npt, a, nb, s)
+                      : launch_step_npt<T, SHIFTED, kGMF, false>(npt, a, nb, s);
+    return sample ? launch_step_npt<T, SHIFTED, kBGK, true>(npt, a, nb, s)
+                  : launch_step_npt<T, SHIFTED, kBGK, false>(npt, a, nb, s);
+}
+
+hipError_t launch_step(int precision, int collision, bool sample, int npt, const StepArgs& a, uint32_t nblocks,
+                       hipStream_t s)
+{
+    if (precision == kFP64) return launch_step_t<double, false>(collision, sample, npt, a, nblocks, s);
+    return launch_step_t<float, true>(collision, sample, npt, a, nblocks, s);
+}
+
+// ---------------------------------------------------------------------------
+// Initial state: rest equilibrium f = w rho0 (shifted: g = 0)
+// ---------------------------------------------------------------------------
+template <typename T, bool SHIFTED>
+__global__ __launch_bounds__(kBlock) void init_kernel(T* buf, const RepDev* rep)
+{
+    const RepDev& R = *rep;
+    const uint32_t n = blockIdx.x * (uint32_t)kBlock + threadIdx.x;
+    if (n >= R.n) return;
+    T* b = buf + R.pop_offset;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) b[(uint64_t)p * R.n + n] = SHIFTED ? T(0) : (T)(tweight(p) * R.rho0);
+}
+
+hipError_t launch_init(int precision, void* buf, const RepDev* rep_dev, const RepDev& rep, hipStream_t s)
+{
+    const uint32_t g = (rep.n + kBlock - 1) / kBlock;
+    if (precision == kFP64)
+        init_kernel<double, false><<<g, kBlock, 0, s>>>((double*)buf, rep_dev);
+    else
+        init_kernel<float, true><<<g, kBlock, 0, s>>>((float*)buf, rep_dev);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sampling: per-replica reduction of the workgroup partials into the FP64
+// accumulators (spatial mean, mean square and variance of each observable).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void stats_reduce_kernel(const RepDev* reps, const double* partials,
+                                                              double* acc)
+{
+    const RepDev& R = reps[blockIdx.x];
+    constexpr int NV = 2 * kObs + 1;
+    double v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = 0.0;
+    for (uint32_t b = threadIdx.x; b < R.nblocks; b += kBlock) {
+        const double* p = partials + (size_t)(R.block_begin + b) * kPartialStride;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] += p[q];
+    }
+    __shared__ double tot[NV];
+    block_sum_store<NV>(v, tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double* A = acc + (size_t)blockIdx.x * kAccStride;
+        const double invn = 1.0 / (double)R.n;
+        A[kAccNsamp] += 1.0;
+        A[kAccNonfinite] += tot[2 * kObs];
+        for (int q = 0; q < kObs; ++q) {
+            const double m = tot[2 * q] * invn, m2 = tot[2 * q + 1] * invn;
+            A[kAccMean + q] += m;
+            A[kAccMeanSq + q] += m2;
+            A[kAccVar + q] += m2 - m * m;
+        }
+    }
+}
+
+hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* partials, double* acc, hipStream_t s)
+{
+    stats_reduce_kernel<<<nrep, kBlock, 0, s>>>(reps, partials, acc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Shell spectra.  Stage 1 (one workgroup per (field, z plane)): for each row y
+// the DFT along x at n_x = 0..3, then along y at n_y = -3..3.  Stage 2 (one
+// workgroup per replica): the DFT along z at n_z = -3..3 for the vectors of the
+// shells |n|^2 in {1,2,3,4,5,6,8,9} with n_x >= 0 (a real field has
+// |m(-k)| = |m(k)|, so n_x > 0 counts twice), shell averages into the
+// accumulators.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dft_plane_kernel(const RepDev* reps, const uint16_t* plane2rep,
+                                                           const T* fields, double2* dft)
+{
+    extern __shared__ double lds[];
+    const uint32_t plane_id = blockIdx.x;
+    const int fld = blockIdx.y;
+    const int r = plane2rep[plane_id];
+    const RepDev& R = reps[r];
+    uint32_t z = plane_id;
+    for (int q = 0; q < r; ++q) z -= reps[q].nz;
+    const uint32_t nx = R.nx, ny = R.ny;
+    double* twx = lds;                 // cos, sin of 2 pi m / nx
+    double* twy = twx + 2 * nx;        // cos, sin of 2 pi m / ny
+    double* X = twy + 2 * ny;          // ny rows x 4 complex
+    for (uint32_t m = threadIdx.x; m < nx; m += kBlock) {
+        double s, c;
+        sincospi(2.0 * (double)m / (double)nx, &s, &c);
+        twx[2 * m] = c;
+        twx[2 * m + 1] = s;
+    }
+    for (uint32_t m = threadIdx.x; m < ny; m += kBlock) {
+        double s, c;
+        sincospi(2.0 * (double)m / (double)ny, &s, &c);
+        twy[2 * m] = c;
+        twy[2 * m + 1] = s;
+    }
+    __syncthreads();
+    const T* src = fields + R.field_offset + (uint64_t)fld * R.n + (uint64_t)z * nx * ny;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (uint32_t y = wave; y < ny; y += kBlock / 64) {
+        double re[kDftNx], im[kDftNx];
+#pragma unroll
+        for (int q = 0; q < kDftNx; ++q) re[q] = im[q] = 0.0;
+        for (uint32_t x = lane; x < nx; x += 64) {
+            const double v = (double)src[(uint64_t)y * nx + x];
+#pragma unroll
+            for (int q = 0; q < kDftNx; ++q) {
+                uint32_t m = (uint32_t)q * x;
+                while (m >= nx) m -= nx;
+                re[q] += v * twx[2 * m];
+                im[q] -= v * twx[2 * m + 1];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kDftNx; ++q) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                re[q] += __shfl_xor(re[q], off, 64);
+                im[q] += __shfl_xor(im[q], off, 64);
+            }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < kDftNx; ++q) {
+                X[(y * kDftNx + q) * 2] = re[q];
+                X[(y * kDftNx + q) * 2 + 1] = im[q];
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kDftPlane) {
+        const int q = threadIdx.x / kDftNy;          // n_x
+        const int s = threadIdx.x % kDftNy - 3;      // n_y
+        double re = 0.0, im = 0.0;
+        for (uint32_t y = 0; y < ny; ++y) {
+            int64_t m = ((int64_t)s * (int64_t)y) % (int64_t)ny;
+            if (m < 0) m += ny;
+            const double c = twy[2 * m], sn = twy[2 * m + 1];
+            const double xr = X[(y * kDftNx + q) * 2], xi = X[(y * kDftNx + q) * 2 + 1];
+            // (xr + i xi)(c - i sn)
+            re += xr * c + xi * sn;
+            im += xi * c - xr * sn;
+        }
+        dft[R.dft_offset + ((uint64_t)fld * R.nz + z) * kDftPlane + threadIdx.x] = make_double2(re, im);
+    }
+}
+
+__device__ __forceinline__ int shell_of(int n2)
+{
+    switch (n2) {
+    case 1: return 0;
+    case 2: return 1;
+    case 3: return 2;
+    case 4: return 3;
+    case 5: return 4;
+    case 6: return 5;
+    case 8: return 6;
+    case 9: return 7;
+    default: return -1;
+    }
+}
+
+__device__ constexpr int kShellCount[kShells] = {6, 12, 8, 6, 24, 24, 12, 30};
+
+__global__ __launch_bounds__(kBlock) void dft_shell_kernel(const RepDev* reps, const double2* dft, double* acc)
+{
+    const RepDev& R = reps[blockIdx.x];
+    constexpr int NVEC = kDftNx * kDftNy * 7;   // n_x 0..3, n_y -3..3, n_z -3..3
+    __shared__ double contrib[NVEC][kSpec];
+    __shared__ int shell[NVEC];
+    const int v = threadIdx.x;
+    if (v < NVEC) {
+        const int q = v / (kDftNy * 7);
+        const int s = (v / 7) % kDftNy - 3;
+        const int u = v % 7 - 3;
+        const int sh = shell_of(q * q + s * s + u * u);
+        shell[v] = sh;
+        double pw[kSpec] = {0, 0, 0, 0, 0};
+        if (sh >= 0) {
+            double zr[kFields], zi[kFields];
+#pragma unroll
+            for (int f = 0; f < kFields; ++f) zr[f] = zi[f] = 0.0;
+            const int col = q * kDftNy + (s + 3);
+            for (uint32_t z = 0; z < R.nz; ++z) {
+                int64_t m = ((int64_t)u * (int64_t)z) % (int64_t)R.nz;
+                if (m < 0) m += R.nz;
+                double sn, c;
+                sincospi(2.0 * (double)m / (double)R.nz, &sn, &c);
+#pragma unroll
+                for (int f = 0; f < kFields; ++f) {
+                    const double2 p = dft[R.dft_offset + ((uint64_t)f * R.nz + z) * kDftPlane + col];
+                    zr[f] += p.x * c + p.y * sn;
+                    zi[f] += p.y * c - p.x * sn;
+                }
+            }
+            const double w = (q > 0 ? 2.0 : 1.0) / (double)R.n;
+            auto pow2 = [](double a, double b) { return a * a + b * b; };
+            pw[0] = w * pow2(zr[0], zi[0]);
+            pw[1] = w * (pow2(zr[1], zi[1]) + pow2(zr[2], zi[2]) + pow2(zr[3], zi[3])) / 3.0;
+            pw[2] = w * pow2(zr[1] + zr[2] + zr[3], zi[1] + zi[2] + zi[3]);
+            pw[3] = w * pow2(zr[4], zi[4]);
+            pw[4] = w * pow2(zr[5], zi[5]);
+        }
+#pragma unroll
+        for (int m = 0; m < kSpec; ++m) contrib[v][m] = pw[m];
+    }
+    __syncthreads();
+    if (threadIdx.x < kSpec * kShells) {
+        const int m = threadIdx.x / kShells, sh = threadIdx.x % kShells;
+        double s = 0.0;
+        for (int j = 0; j < NVEC; ++j)
+            if (shell[j] == sh) s += contrib[j][m];
+        acc[(size_t)blockIdx.x * kAccStride + kAccSpec + m * kShells + sh] += s / (double)kShellCount[sh];
+    }
+}
+
+hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint16_t* plane2rep, uint32_t nplanes,
+                      const void* fields, double* dft, double* acc, int max_nx, int max_ny, hipStream_t s)
+{
+    const size_t lds = sizeof(double) * (2 * (size_t)max_nx + 2 * (size_t)max_ny + 2 * kDftNx * (size_t)max_ny);
+    dim3 grid(nplanes, kFields);
+    if (precision == kFP64)
+        dft_plane_kernel<double><<<grid, kBlock, lds, s>>>(reps, plane2rep, (const double*)fields, (double2*)dft);
+    else
+        dft_plane_kernel<float><<<grid, kBlock, lds, s>>>(reps, plane2rep, (const float*)fields, (double2*)dft);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dft_shell_kernel<<<nrep, kBlock, 0, s>>>(reps, (const double2*)dft, acc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Step counter kept on the device so that captured graphs can be replayed
+// ---------------------------------------------------------------------------
+__global__ void set_step_kernel(int64_t* d, int64_t v)
+{
+    if (threadIdx.x == 0) *d = v;
+}
+__global__ void advance_step_kernel(int64_t* d, int64_t by)
+{
+    if (threadIdx.x == 0) *d += by;
+}
+
+hipError_t launch_set_step(int64_t* d_step, int64_t value, hipStream_t s)
+{
+    set_step_kernel<<<1, 64, 0, s>>>(d_step, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_step(int64_t* d_step, int64_t by, hipStream_t s)
+{
+    advance_step_kernel<<<1, 64, 0, s>>>(d_step, by);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Canonical order of the interface: rest; faces +x,-x,+y,-y,+z,-z; edges and
+// corners in lexicographic order of (cx, cy, cz).
+// ---------------------------------------------------------------------------
+void canonical_to_tensor(int out[Q])
+{
+    int i = 0;
+    out[i++] = tindex(0, 0, 0);
+    const int faces[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+    for (auto& c : faces) out[i++] = tindex(c[0], c[1], c[2]);
+    for (int nnz = 2; nnz <= 3; ++nnz)
+        for (int cx = -1; cx <= 1; ++cx)
+            for (int cy = -1; cy <= 1; ++cy)
+                for (int cz = -1; cz <= 1; ++cz)
+                    if ((cx != 0) + (cy != 0) + (cz != 0) == nnz) out[i++] = tindex(cx, cy, cz);
+}
+
+struct CanonMap {
+    int8_t tensor_of[Q];   // canonical i -> tensor p
+};
+
+static CanonMap make_canon_map()
+{
+    CanonMap m;
+    int t[Q];
+    canonical_to_tensor(t);
+    for (int i = 0; i < Q; ++i) m.tensor_of[i] = (int8_t)t[i];
+    return m;
+}
+
+// canonical f(x) = stored_p(x - c_p) (+ w_p rho0 when shifted), planes z0 <= z < z1
+template <typename T, bool SHIFTED>
+__global__ __launch_bounds__(kBlock) void gather_kernel(const T* src, const RepDev* rep, uint32_t z0, uint32_t z1,
+                                                        double* out, CanonMap cm)
+{
+    const RepDev& R = *rep;
+    const uint64_t plane = (uint64_t)R.nx * R.ny;
+    const uint64_t cnt = plane * (z1 - z0);
+    const uint64_t idx = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= cnt) return;
+    const uint32_t x = (uint32_t)(idx % R.nx);
+    const uint32_t y = (uint32_t)((idx / R.nx) % R.ny);
+    const uint32_t z = z0 + (uint32_t)(idx / plane);
+    const T* s = src + R.pop_offset;
+    for (int i = 0; i < Q; ++i) {
+        const int p = cm.tensor_of[i];
+        const uint32_t xs = (x + R.nx - tcx(p)) % R.nx;
+        const uint32_t ys = (y + R.ny - tcy(p)) % R.ny;
+        const uint32_t zs = (z + R.nz - tcz(p)) % R.nz;
+        const uint64_t node = xs + (uint64_t)R.nx * (ys + (uint64_t)R.ny * zs);
+        double v = (double)s[(uint64_t)p * R.n + node];
+        if (SHIFTED) v += tweight(p) * R.rho0;
+        out[(uint64_t)i * cnt + idx] = v;
+    }
+}
+
+template <typename T, bool SHIFTED>
+__global__ __launch_bounds__(kBlock) void scatter_kernel(T* dst, const RepDev* rep, uint32_t z0, uint32_t z1,
+                                                         const double* in, CanonMap cm)
+{
+    const RepDev& R = *rep;
+    const uint64_t plane = (uint64_t)R.nx * R.ny;
+    const uint64_t cnt = plane * (z1 - z0);
+    const uint64_t idx = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= cnt) return;
+    const uint32_t x = (uint32_t)(idx % R.nx);
+    const uint32_t y = (uint32_t)((idx / R.nx) % R.ny);
+    const uint32_t z = z0 + (uint32_t)(idx / plane);
+    T* d = dst + R.pop_offset;
+    for (int i = 0; i < Q; ++i) {
+        const int p = cm.tensor_of[i];
+        const uint32_t xs = (x + R.nx - tcx(p)) % R.nx;
+        const uint32_t ys = (y + R.ny - tcy(p)) % R.ny;
+        const uint32_t zs = (z + R.nz - tcz(p)) % R.nz;
+        const uint64_t node = xs + (uint64_t)R.nx * (ys + (uint64_t)R.ny * zs);
+        double v = in[(uint64_t)i * cnt + idx];
+        if (SHIFTED) v -= tweight(p) * R.rho0;
+        d[(uint64_t)p * R.n + node] = (T)v;
+    }
+}
+
+// density and velocity of the canonical state plus FP64 workgroup sums of rho, j
+template <typename T, bool SHIFTED>
+__global__ __launch_bounds__(kBlock) void moments_kernel(const T* src, const RepDev* rep, uint32_t z0, uint32_t z1,
+                                                         double* rho_out, double* u_out, double* partials)
+{
+    const RepDev& R = *rep;
+    const uint64_t plane = (uint64_t)R.nx * R.ny;
+    const uint64_t cnt = plane * (z1 - z0);
+    const uint64_t idx = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (idx < cnt) {
+        const uint32_t x = (uint32_t)(idx % R.nx);
+        const uint32_t y = (uint32_t)((idx / R.nx) % R.ny);
+        const uint32_t z = z0 + (uint32_t)(idx / plane);
+        const T* s = src + R.pop_offset;
+        double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        for (int p = 0; p < Q; ++p) {
+            const uint32_t xs = (x + R.nx - tcx(p)) % R.nx;
+            const uint32_t ys = (y + R.ny - tcy(p)) % R.ny;
+            const uint32_t zs = (z + R.nz - tcz(p)) % R.nz;
+            const uint64_t node = xs + (uint64_t)R.nx * (ys + (uint64_t)R.ny * zs);
+            double fv = (double)s[(uint64_t)p * R.n + node];
+            if (SHIFTED) fv += tweight(p) * R.rho0;
+            rho += fv;
+            jx += fv * tcx(p);
+            jy += fv * tcy(p);
+            jz += fv * tcz(p);
+        }
+        if (rho_out) rho_out[idx] = rho;
+        if (u_out) {
+            u_out[idx] = jx / rho;
+            u_out[cnt + idx] = jy / rho;
+            u_out[2 * cnt + idx] = jz / rho;
+        }
+        v[0] = rho; v[1] = jx; v[2] = jy; v[3] = jz;
+    }
+    block_sum_store<4>(v, partials + (size_t)blockIdx.x * 4);
+}
+
+__global__ __launch_bounds__(kBlock) void sum_partials_kernel(const double* partials, uint32_t nb, double* out4,
+                                                              int accumulate)
+{
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint32_t b = threadIdx.x; b < nb; b += kBlock)
+        for (int q = 0; q < 4; ++q) v[q] += partials[(size_t)b * 4 + q];
+    __shared__ double tot[4];
+    block_sum_store<4>(v, tot);
+    __syncthreads();
+    if (threadIdx.x < 4) out4[threadIdx.x] = (accumulate ? out4[threadIdx.x] : 0.0) + tot[threadIdx.x];
+}
+
+template <typename T, bool SHIFTED>
+__global__ __launch_bounds__(kBlock) void nodes_kernel(const T* src, const RepDev* rep, const int64_t* nodes,
+                                                       int32_t count, double* out, CanonMap cm)
+{
+    const RepDev& R = *rep;
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= count) return;
+    const uint64_t n = (uint64_t)nodes[j];
+    const uint32_t x = (uint32_t)(n % R.nx);
+    const uint32_t y = (uint32_t)((n / R.nx) % R.ny);
+    const uint32_t z = (uint32_t)(n / ((uint64_t)R.nx * R.ny));
+    const T* s = src + R.pop_offset;
+    for (int i = 0; i < Q; ++i) {
+        const int p = cm.tensor_of[i];
+        const uint32_t xs = (x + R.nx - tcx(p)) % R.nx;
+        const uint32_t ys = (y + R.ny - tcy(p)) % R.ny;
+        const uint32_t zs = (z + R.nz - tcz(p)) % R.nz;
+        const uint64_t node = xs + (uint64_t)R.nx * (ys + (uint64_t)R.ny * zs);
+        double v = (double)s[(uint64_t)p * R.n + node];
+        if (SHIFTED) v += tweight(p) * R.rho0;
+        out[(size_t)j * Q + i] = v;
+    }
+}
+
+static inline uint32_t grid_for(uint64_t cnt) { return (uint32_t)((cnt + kBlock - 1) / kBlock); }
+
+hipError_t launch_gather(int precision, const void* src, const RepDev* rep_dev, const RepDev& rep, uint32_t z0,
+                         uint32_t z1, double* out, hipStream_t s)
+{
+    const uint32_t g = grid_for((uint64_t)rep.nx * rep.ny * (z1 - z0));
+    static const CanonMap cm = make_canon_map();
+    if (precision == kFP64)
+        gather_kernel<double, false><<<g, kBlock, 0, s>>>((const double*)src, rep_dev, z0, z1, out, cm);
+    else
+        gather_kernel<float, true><<<g, kBlock, 0, s>>>((const float*)src, rep_dev, z0, z1, out, cm);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(int precision, void* dst, const RepDev* rep_dev, const RepDev& rep, uint32_t z0,
+                          uint32_t z1, const double* in, hipStream_t s)
+{
+    const uint32_t g = grid_for((uint64_t)rep.nx * rep.ny * (z1 - z0));
+    static const CanonMap cm = make_canon_map();
+    if (precision == kFP64)
+        scatter_kernel<double, false><<<g, kBlock, 0, s>>>((double*)dst, rep_dev, z0, z1, in, cm);
+    else
+        scatter_kernel<float, true><<<g, kBlock, 0, s>>>((float*)dst, rep_dev, z0, z1, in, cm);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int precision, const void* src, const RepDev* rep_dev, const RepDev& rep, uint32_t z0,
+                          uint32_t z1, double* rho, double* u, double* partials, hipStream_t s)
+{
+    const uint32_t g = grid_for((uint64_t)rep.nx * rep.ny * (z1 - z0));
+    if (precision == kFP64)
+        moments_kernel<double, false><<<g, kBlock, 0, s>>>((const double*)src, rep_dev, z0, z1, rho, u, partials);
+    else
+        moments_kernel<float, true><<<g, kBlock, 0, s>>>((const float*)src, rep_dev, z0, z1, rho, u, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double* partials, uint32_t nblocks, double* out4, int accumulate, hipStream_t s)
+{
+    sum_partials_kernel<<<1, kBlock, 0, s>>>(partials, nblocks, out4, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_nodes(int precision, const void* src, const RepDev* rep_dev, const int64_t* nodes, int32_t count,
+                        double* out, hipStream_t s)
+{
+    static const CanonMap cm = make_canon_map();
+    const uint32_t g = grid_for((uint64_t)count);
+    if (precision == kFP64)
+        nodes_kernel<double, false><<<g, kBlock, 0, s>>>((const double*)src, rep_dev, nodes, count, out, cm);
+    else
+        nodes_kernel<float, true><<<g, kBlock, 0, s>>>((const float*)src, rep_dev, nodes, count, out, cm);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The step kernels' noise generator, exposed for inspection.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void noise_probe_kernel(uint32_t k0, uint32_t k1, int64_t t, uint32_t node0,
+                                                             int32_t count, uint32_t* words, double* normals)
+{
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= count) return;
+    const uint32_t n = node0 + (uint32_t)j;
+    if (words) {
+        for (int b = 0; b < 6; ++b) {
+            const U4 w = noise_block(n, (uint64_t)t, (uint32_t)b, k0, k1);
+            words[(size_t)j * 24 + 4 * b + 0] = w.x;
+            words[(size_t)j * 24 + 4 * b + 1] = w.y;
+            words[(size_t)j * 24 + 4 * b + 2] = w.z;
+            words[(size_t)j * 24 + 4 * b + 3] = w.w;
+        }
+    }
+    if (normals) {
+        T r[23];
+        node_normals<T>(n, (uint64_t)t, k0, k1, r);
+        for (int k = 0; k < 23; ++k) normals[(size_t)j * 23 + k] = (double)r[k];
+    }
+}
+
+hipError_t launch_noise_probe(int precision, uint64_t seed, int64_t t, uint32_t node0, int32_t count,
+                              uint32_t* words, double* normals, hipStream_t s)
+{
+    const uint32_t g = grid_for((uint64_t)count);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    if (precision == kFP64)
+        noise_probe_kernel<double><<<g, kBlock, 0, s>>>(k0, k1, t, node0, count, words, normals);
+    else
+        noise_probe_kernel<float><<<g, kBlock, 0, s>>>(k0, k1, t, node0, count, words, normals);
+    return hipGetLastError();
+}
+
+}  // namespace gmf

@@ -1,0 +1,763 @@
+// gmf_runtime.cpp -- host runtime and C ABI of the GMF-FLBM library (see gmf.h).
+//
+// A context owns: the replica table, two population buffers (A/B pull
+// scheme: the step with index t reads buffer t%2 and writes the other), the
+// sampling buffers and FP64 accumulators, a staging area for host transfers,
+// the device step counter and the captured step-loop graphs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gmf.h"
+#include "gmf_device.hpp"
+#include "gmf_internal.hpp"
+
+using namespace gmf;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kStageCap = 64ull << 20;   // staging for host transfers (per chunk of z planes)
+constexpr int kDefaultGraphSteps = 64;
+constexpr int kDefaultNpt = 1;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+const double kCs2 = 1.0 / 3.0;
+// b_k of the Table II groups feeding RepDev::amp: k=4..6, 7..9, 10..15, 16, 17..19, 20..22, 23..25, 26
+const double kGroupB[8] = {2.0 / 9, 1.0 / 9, 2.0 / 27, 1.0 / 27, 4.0 / 81, 2.0 / 81, 4.0 / 243, 8.0 / 729};
+const int kShellN2[kShells] = {1, 2, 3, 4, 5, 6, 8, 9};
+const int kShellCnt[kShells] = {6, 12, 8, 6, 24, 24, 12, 30};
+
+struct Layout {
+    size_t pop_bytes = 0, popA = 0, popB = 0, reps = 0, blk2rep = 0, step = 0, acc = 0, tot = 0, mpart = 0;
+    size_t fields = 0, partials = 0, dft = 0, plane2rep = 0, stage = 0, stage_bytes = 0, total = 0;
+    uint64_t total_nodes = 0;
+    uint32_t max_blocks = 0;     // lattice grid at one node per thread
+    uint32_t total_planes = 0;
+    uint32_t dft_complex = 0;
+    uint32_t max_chunk_blocks = 0;
+    int max_nx = 0, max_ny = 0;
+    bool sampling = false;
+};
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
+{
+    if (!reps || nrep < 1 || nrep > 65535) return GMF_EINVAL;
+    if (opt) {
+        if (opt->precision != GMF_FP64 && opt->precision != GMF_FP32_SHIFTED) return GMF_EINVAL;
+        if (opt->collision != GMF_COLLISION_GMF && opt->collision != GMF_COLLISION_BGK) return GMF_EINVAL;
+        if (opt->noise_rho != 0 && opt->noise_rho != 1) return GMF_EINVAL;
+        if (opt->sample_every < 0 || opt->tune < 0 || opt->tune > 1) return GMF_EINVAL;
+        if (opt->reserved[0] != 0 || opt->reserved[1] != 0) return GMF_EINVAL;
+    }
+    const size_t es = (opt && opt->precision == GMF_FP32_SHIFTED) ? 4 : 8;
+    const bool sampling = opt && opt->sample_every > 0;
+    for (int r = 0; r < nrep; ++r) {
+        const gmf_replica& R = reps[r];
+        if (R.nx < 1 || R.ny < 1 || R.nz < 1 || R.reserved != 0) return GMF_EINVAL;
+        const uint64_t n = (uint64_t)R.nx * R.ny * R.nz;
+        // 32-bit node indices and 32-bit byte offsets inside one population array
+        if (n >= (1ull << 31) || n * es >= (1ull << 32)) return GMF_EINVAL;
+        if (!finite_pos(R.rho0) || !std::isfinite(R.tau) || !(R.tau > 0.5)) return GMF_EINVAL;
+        if (!std::isfinite(R.kbt) || R.kbt < 0.0) return GMF_EINVAL;
+        // the spectra keep two twiddle tables and one row of partial sums per y in LDS
+        if (sampling && 2 * (uint64_t)R.nx + 10 * (uint64_t)R.ny > 8192) return GMF_EINVAL;
+    }
+    return GMF_OK;
+}
+
+Layout plan(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
+{
+    Layout L;
+    const size_t es = (opt && opt->precision == GMF_FP32_SHIFTED) ? 4 : 8;
+    L.sampling = opt && opt->sample_every > 0;
+    uint64_t stage_nodes = 0;
+    for (int r = 0; r < nrep; ++r) {
+        const uint64_t n = (uint64_t)reps[r].nx * reps[r].ny * reps[r].nz;
+        const uint64_t plane = (uint64_t)reps[r].nx * reps[r].ny;
+        L.total_nodes += n;
+        L.max_blocks += (uint32_t)((n + kBlock - 1) / kBlock);
+        L.total_planes += (uint32_t)reps[r].nz;
+        L.dft_complex += (uint32_t)(kFields * reps[r].nz * kDftPlane);
+        L.max_nx = std::max(L.max_nx, (int)reps[r].nx);
+        L.max_ny = std::max(L.max_ny, (int)reps[r].ny);
+        // a chunk holds whole z planes: at least one plane, at most kStageCap bytes of FP64 populations
+        uint64_t planes = std::max<uint64_t>(1, kStageCap / (Q * 8 * plane));
+        planes = std::min<uint64_t>(planes, (uint64_t)reps[r].nz);
+        stage_nodes = std::max(stage_nodes, planes * plane);
+    }
+    // at least 64 KiB so that node lists (gmf_get_nodes) always have room
+    L.stage_bytes = std::max<uint64_t>(stage_nodes * Q * 8, 64u << 10);
+    // chunk_planes() never puts more than stage_bytes / (27 * 8) nodes in a chunk
+    const uint64_t chunk_nodes_max = L.stage_bytes / (Q * 8);
+    L.max_chunk_blocks = (uint32_t)((chunk_nodes_max + kBlock - 1) / kBlock);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1));
+        return o;
+    };
+    L.pop_bytes = (size_t)L.total_nodes * Q * es;
+    L.popA = take(L.pop_bytes);
+    L.popB = take(L.pop_bytes);
+    L.reps = take(sizeof(RepDev) * nrep);
+    L.blk2rep = take(sizeof(uint16_t) * L.max_blocks);
+    L.step = take(sizeof(int64_t));
+    L.acc = take(sizeof(double) * kAccStride * nrep);
+    L.tot = take(sizeof(double) * 4);
+    L.mpart = take(sizeof(double) * 4 * L.max_chunk_blocks);
+    if (L.sampling) {
+        L.fields = take((size_t)L.total_nodes * kFields * es);
+        L.partials = take(sizeof(double) * kPartialStride * L.max_blocks);
+        L.dft = take(sizeof(double) * 2 * L.dft_complex);
+        L.plane2rep = take(sizeof(uint16_t) * L.total_planes);
+    }
+    L.stage = take(L.stage_bytes);
+    L.total = off;
+    return L;
+}
+
+gmf_options default_options()
+{
+    gmf_options o;
+    std::memset(&o, 0, sizeof(o));
+    o.precision = GMF_FP64;
+    o.collision = GMF_COLLISION_GMF;
+    o.graph_steps = -1;
+    return o;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct gmf_ctx {
+    gmf_options opt;
+    int32_t nrep = 0;
+    std::vector<gmf_replica> reps;
+    std::vector<RepDev> rdev;
+    Layout L;
+    int device = 0;
+    char* ws = nullptr;
+    bool own_ws = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int npt = kDefaultNpt;
+    uint32_t nblocks = 0;          // lattice grid for the current npt
+    int graph_steps = 0;           // 0: direct launches
+    int period = 2;                // step pattern period (A/B parity, sampling)
+    int64_t step = 0;
+    bool dev_step_valid = false;   // device counter == step
+    std::map<int, hipGraphExec_t> graphs;
+    bool poisoned = false;
+
+    void* pop(int which) { return ws + (which ? L.popB : L.popA); }
+    RepDev* d_reps() { return reinterpret_cast<RepDev*>(ws + L.reps); }
+    uint16_t* d_blk2rep() { return nrep > 1 ? reinterpret_cast<uint16_t*>(ws + L.blk2rep) : nullptr; }
+    int64_t* d_step() { return reinterpret_cast<int64_t*>(ws + L.step); }
+    double* d_acc() { return reinterpret_cast<double*>(ws + L.acc); }
+    double* d_tot() { return reinterpret_cast<double*>(ws + L.tot); }
+    double* d_mpart() { return reinterpret_cast<double*>(ws + L.mpart); }
+    void* d_fields() { return L.sampling ? ws + L.fields : nullptr; }
+    double* d_partials() { return L.sampling ? reinterpret_cast<double*>(ws + L.partials) : nullptr; }
+    double* d_dft() { return L.sampling ? reinterpret_cast<double*>(ws + L.dft) : nullptr; }
+    uint16_t* d_plane2rep() { return L.sampling ? reinterpret_cast<uint16_t*>(ws + L.plane2rep) : nullptr; }
+    char* d_stage() { return ws + L.stage; }
+};
+
+#define CK(expr)                                                                                 \
+    do {                                                                                         \
+        hipError_t _e = (expr);                                                                  \
+        if (_e != hipSuccess) {                                                                  \
+            if (getenv("GMF_DEBUG")) fprintf(stderr, "gmf: %s failed: %s\n", #expr, hipGetErrorString(_e)); \
+            ctx->poisoned = true;                                                                \
+            return GMF_EDEVICE;                                                                  \
+        }                                                                                        \
+    } while (0)
+
+namespace {
+
+// Workgroup -> replica map and per-replica grid ranges for `npt` nodes per thread.
+int build_grid(gmf_ctx* ctx, int npt)
+{
+    std::vector<uint16_t> map;
+    uint32_t b = 0;
+    for (int r = 0; r < ctx->nrep; ++r) {
+        RepDev& R = ctx->rdev[r];
+        const uint32_t per = (uint32_t)kBlock * (uint32_t)npt;
+        R.block_begin = b;
+        R.nblocks = (R.n + per - 1) / per;
+        b += R.nblocks;
+        if (ctx->nrep > 1) map.insert(map.end(), R.nblocks, (uint16_t)r);
+    }
+    ctx->nblocks = b;
+    ctx->npt = npt;
+    CK(hipMemcpyAsync(ctx->d_reps(), ctx->rdev.data(), sizeof(RepDev) * ctx->nrep, hipMemcpyHostToDevice,
+                      ctx->stream));
+    if (ctx->nrep > 1)
+        CK(hipMemcpyAsync(ctx->d_blk2rep(), map.data(), sizeof(uint16_t) * map.size(), hipMemcpyHostToDevice,
+                          ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+    ctx->graphs.clear();
+    return GMF_OK;
+}
+
+bool sampling_step(const gmf_ctx* ctx, int64_t t)
+{
+    return ctx->opt.sample_every > 0 && t % ctx->opt.sample_every == 0;
+}
+
+// Enqueue the step with index t.  In a graph (in_graph) the kernels read the
+// step from the device counter plus offset j.
+int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
+{
+    const int par = (int)(t & 1);
+    StepArgs a;
+    a.src = ctx->pop(par);
+    a.dst = ctx->pop(par ^ 1);
+    a.reps = ctx->d_reps();
+    a.blk2rep = ctx->d_blk2rep();
+    a.d_step = in_graph ? ctx->d_step() : nullptr;
+    a.step_base = in_graph ? (int64_t)j : t;
+    a.fields = ctx->d_fields();
+    a.partials = ctx->d_partials();
+    const bool sample = sampling_step(ctx, t);
+    CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, ctx->npt, a, ctx->nblocks, ctx->stream));
+    if (sample) {
+        CK(launch_stats_reduce(ctx->d_reps(), ctx->nrep, ctx->d_partials(), ctx->d_acc(), ctx->stream));
+        CK(launch_dft(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_plane2rep(), ctx->L.total_planes,
+                      ctx->d_fields(), ctx->d_dft(), ctx->d_acc(), ctx->L.max_nx, ctx->L.max_ny, ctx->stream));
+    }
+    return GMF_OK;
+}
+
+int capture_graph(gmf_ctx* ctx, int phase, hipGraphExec_t* out)
+{
+    hipGraph_t g = nullptr;
+    CK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    int rc = GMF_OK;
+    for (int j = 0; j < ctx->graph_steps && rc == GMF_OK; ++j) rc = enqueue_step(ctx, (int64_t)phase + j, true, j);
+    if (rc == GMF_OK) {
+        hipError_t e = launch_advance_step(ctx->d_step(), ctx->graph_steps, ctx->stream);
+        if (e != hipSuccess) rc = GMF_EDEVICE;
+    }
+    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    if (rc != GMF_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        ctx->poisoned = true;
+        return GMF_EDEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        ctx->poisoned = true;
+        return GMF_EDEVICE;
+    }
+    *out = ex;
+    return GMF_OK;
+}
+
+int run_steps(gmf_ctx* ctx, int64_t n)
+{
+    while (n > 0) {
+        if (ctx->graph_steps > 0 && n >= ctx->graph_steps) {
+            const int phase = (int)(ctx->step % ctx->period);
+            auto it = ctx->graphs.find(phase);
+            if (it == ctx->graphs.end()) {
+                hipGraphExec_t ex;
+                int rc = capture_graph(ctx, phase, &ex);
+                if (rc != GMF_OK) return rc;
+                it = ctx->graphs.emplace(phase, ex).first;
+            }
+            if (!ctx->dev_step_valid) {
+                CK(launch_set_step(ctx->d_step(), ctx->step, ctx->stream));
+                ctx->dev_step_valid = true;
+            }
+            CK(hipGraphLaunch(it->second, ctx->stream));
+            ctx->step += ctx->graph_steps;
+            n -= ctx->graph_steps;
+        } else {
+            int rc = enqueue_step(ctx, ctx->step, false, 0);
+            if (rc != GMF_OK) return rc;
+            ctx->step += 1;
+            n -= 1;
+            ctx->dev_step_valid = false;
+        }
+    }
+    return GMF_OK;
+}
+
+// Time each nodes-per-thread variant on the current state (the step is
+// re-run from the same source buffer, so the state does not advance).
+int autotune(gmf_ctx* ctx)
+{
+    const char* cache = getenv("GMF_TUNE_CACHE");
+    std::string key = "p" + std::to_string(ctx->opt.precision) + "c" + std::to_string(ctx->opt.collision);
+    for (auto& r : ctx->reps) key += "_" + std::to_string(r.nx) + "x" + std::to_string(r.ny) + "x" + std::to_string(r.nz);
+    if (cache) {
+        if (FILE* fh = fopen(cache, "r")) {
+            char k[4096];
+            int v;
+            while (fscanf(fh, "%4095s %d", k, &v) == 2)
+                if (key == k) {
+                    fclose(fh);
+                    return build_grid(ctx, v);
+                }
+            fclose(fh);
+        }
+    }
+    const int cand[3] = {1, 2, 4};
+    hipEvent_t e0, e1;
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int best = kDefaultNpt;
+    const int reps = 8;
+    for (int c : cand) {
+        int rc = build_grid(ctx, c);
+        if (rc != GMF_OK) return rc;
+        StepArgs a;
+        a.src = ctx->pop((int)(ctx->step & 1));
+        a.dst = ctx->pop((int)(ctx->step & 1) ^ 1);
+        a.reps = ctx->d_reps();
+        a.blk2rep = ctx->d_blk2rep();
+        a.d_step = nullptr;
+        a.step_base = ctx->step;
+        a.fields = nullptr;
+        a.partials = nullptr;
+        CK(launch_step(ctx->opt.precision, ctx->opt.collision, false, c, a, ctx->nblocks, ctx->stream));
+        CK(hipEventRecord(e0, ctx->stream));
+        for (int i = 0; i < reps; ++i)
+            CK(launch_step(ctx->opt.precision, ctx->opt.collision, false, c, a, ctx->nblocks, ctx->stream));
+        CK(hipEventRecord(e1, ctx->stream));
+        CK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        CK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (cache) {
+        if (FILE* fh = fopen(cache, "a")) {
+            fprintf(fh, "%s %d\n", key.c_str(), best);
+            fclose(fh);
+        }
+    }
+    return build_grid(ctx, best);
+}
+
+uint32_t chunk_planes(const gmf_ctx* ctx, int r)
+{
+    const uint64_t plane = (uint64_t)ctx->reps[r].nx * ctx->reps[r].ny;
+    uint64_t p = std::max<uint64_t>(1, ctx->L.stage_bytes / (Q * 8 * plane));
+    return (uint32_t)std::min<uint64_t>(p, (uint64_t)ctx->reps[r].nz);
+}
+
+int check_ctx(gmf_ctx* ctx)
+{
+    if (!ctx) return GMF_ESTATE;
+    if (ctx->poisoned) return GMF_EDEVICE;
+    return GMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gmf_workspace_bytes(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
+{
+    if (validate(reps, nrep, opt) != GMF_OK) return 0;
+    return plan(reps, nrep, opt).total;
+}
+
+int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, void* dev_workspace,
+             size_t ws_bytes, void* hip_stream, gmf_ctx** out)
+{
+    if (!out) return GMF_EINVAL;
+    *out = nullptr;
+    int rc = validate(reps, nrep, opt_in);
+    if (rc != GMF_OK) return rc;
+    gmf_options opt = opt_in ? *opt_in : default_options();
+    Layout L = plan(reps, nrep, &opt);
+    if (dev_workspace && (ws_bytes < L.total || ((uintptr_t)dev_workspace % kAlign) != 0)) return GMF_EINVAL;
+
+    gmf_ctx* ctx = new (std::nothrow) gmf_ctx();
+    if (!ctx) return GMF_ENOMEM;
+    ctx->opt = opt;
+    ctx->nrep = nrep;
+    ctx->reps.assign(reps, reps + nrep);
+    ctx->L = L;
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return GMF_EDEVICE;
+    }
+    if (dev_workspace) {
+        ctx->ws = static_cast<char*>(dev_workspace);
+    } else {
+        if (hipMalloc((void**)&ctx->ws, L.total) != hipSuccess) {
+            (void)hipGetLastError();
+            delete ctx;
+            return GMF_ENOMEM;
+        }
+        ctx->own_ws = true;
+    }
+    if (hip_stream) {
+        ctx->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            gmf_destroy(ctx);
+            return GMF_EDEVICE;
+        }
+        ctx->own_stream = true;
+    }
+
+    // replica records
+    uint64_t pop_off = 0, field_off = 0;
+    uint32_t dft_off = 0;
+    std::vector<uint16_t> plane2rep;
+    for (int r = 0; r < nrep; ++r) {
+        const gmf_replica& in = reps[r];
+        RepDev R;
+        std::memset(&R, 0, sizeof(R));
+        R.nx = (uint32_t)in.nx;
+        R.ny = (uint32_t)in.ny;
+        R.nz = (uint32_t)in.nz;
+        R.n = R.nx * R.ny * R.nz;
+        R.divx = make_fastdiv(R.nx);
+        R.divy = make_fastdiv(R.ny);
+        R.pop_offset = pop_off;
+        R.field_offset = field_off;
+        R.dft_offset = dft_off;
+        pop_off += (uint64_t)Q * R.n;
+        field_off += (uint64_t)kFields * R.n;
+        dft_off += (uint32_t)(kFields * R.nz * kDftPlane);
+        R.key0 = (uint32_t)in.seed;
+        R.key1 = (uint32_t)(in.seed >> 32);
+        R.noise_on = in.kbt > 0.0 ? 1u : 0u;
+        R.noise_rho0 = (uint32_t)opt.noise_rho;
+        R.rho0 = in.rho0;
+        R.omega = 1.0 / in.tau;
+        R.one_m_omega = 1.0 - R.omega;
+        // phi_k / sqrt(rho): Eq. (2) for k = 4..9 (and every k under BGK), Eq. (9) for GMF ghosts
+        const double relax = R.omega * (2.0 - R.omega);
+        for (int g = 0; g < 8; ++g) {
+            const bool hydro = g < 2 || opt.collision == GMF_COLLISION_BGK;
+            R.amp[g] = std::sqrt(in.kbt * (hydro ? relax : 1.0) * kGroupB[g] / kCs2);
+        }
+        ctx->rdev.push_back(R);
+        if (L.sampling) plane2rep.insert(plane2rep.end(), R.nz, (uint16_t)r);
+    }
+    if (L.sampling) {
+        hipError_t e = hipMemcpy(ctx->d_plane2rep(), plane2rep.data(), sizeof(uint16_t) * plane2rep.size(),
+                                 hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            gmf_destroy(ctx);
+            return GMF_EDEVICE;
+        }
+    }
+    // graphs: K a multiple of the pattern period (A/B parity and the sampling cadence)
+    ctx->period = 2;
+    if (opt.sample_every > 0) {
+        int s = opt.sample_every, a = 2, b = s;
+        while (b) {
+            int t = a % b;
+            a = b;
+            b = t;
+        }
+        ctx->period = 2 / a * s;
+    }
+    int gs = opt.graph_steps < 0 ? kDefaultGraphSteps : opt.graph_steps;
+    if (gs > 0) gs = ((gs + ctx->period - 1) / ctx->period) * ctx->period;
+    ctx->graph_steps = gs;
+
+    rc = build_grid(ctx, kDefaultNpt);
+    if (rc != GMF_OK) {
+        gmf_destroy(ctx);
+        return rc;
+    }
+    for (int r = 0; r < nrep; ++r) {
+        if (launch_init(opt.precision, ctx->pop(0), ctx->d_reps() + r, ctx->rdev[r], ctx->stream) != hipSuccess) {
+            gmf_destroy(ctx);
+            return GMF_EDEVICE;
+        }
+    }
+    if (hipMemsetAsync(ctx->d_acc(), 0, sizeof(double) * kAccStride * nrep, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        gmf_destroy(ctx);
+        return GMF_EDEVICE;
+    }
+    if (opt.tune) {
+        rc = autotune(ctx);
+        if (rc != GMF_OK) {
+            gmf_destroy(ctx);
+            return rc;
+        }
+    }
+    *out = ctx;
+    return GMF_OK;
+}
+
+int gmf_step(gmf_ctx* ctx, int64_t n)
+{
+    int rc = check_ctx(ctx);
+    if (rc != GMF_OK) return rc;
+    if (n < 0) return GMF_EINVAL;
+    DeviceGuard g(ctx->device);
+    return run_steps(ctx, n);
+}
+
+int gmf_moments(gmf_ctx* ctx, int32_t r, double* rho, double* u)
+{
+    int rc = check_ctx(ctx);
+    if (rc != GMF_OK) return rc;
+    if (r < 0 || r >= ctx->nrep) return GMF_EINVAL;
+    DeviceGuard g(ctx->device);
+    const RepDev& R = ctx->rdev[r];
+    const uint64_t plane = (uint64_t)R.nx * R.ny;
+    const uint32_t cp = chunk_planes(ctx, r);
+    double* srho = reinterpret_cast<double*>(ctx->d_stage());
+    for (uint32_t z0 = 0; z0 < R.nz; z0 += cp) {
+        const uint32_t z1 = std::min(R.nz, z0 + cp);
+        const uint64_t cnt = plane * (z1 - z0);
+        double* su = srho + cnt;
+        CK(launch_moments(ctx->opt.precision, ctx->pop((int)(ctx->step & 1)), ctx->d_reps() + r, R, z0, z1, srho,
+                          su, ctx->d_mpart(), ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+        if (rho) CK(hipMemcpy(rho + plane * z0, srho, sizeof(double) * cnt, hipMemcpyDeviceToHost));
+        if (u)
+            for (int a = 0; a < 3; ++a)
+                CK(hipMemcpy(u + (uint64_t)a * R.n + plane * z0, su + a * cnt, sizeof(double) * cnt,
+                             hipMemcpyDeviceToHost));
+    }
+    return GMF_OK;
+}
+
+int gmf_stats(gmf_ctx* ctx, int32_t r, gmf_stats_t* out)
+{
+    int rc = check_ctx(ctx);
+    if (rc != GMF_OK) return rc;
+    if (r < 0 || r >= ctx->nrep || !out) return GMF_EINVAL;
+    DeviceGuard g(ctx->device);
+    const RepDev& R = ctx->rdev[r];
+    const uint64_t plane = (uint64_t)R.nx * R.ny;
+    const uint32_t cp = chunk_planes(ctx, r);
+    bool first = true;
+    for (uint32_t z0 = 0; z0 < R.nz; z0 += cp) {
+        const uint32_t z1 = std::min(R.nz, z0 + cp);
+        const uint64_t cnt = plane * (z1 - z0);
+        const uint32_t nb = (uint32_t)((cnt + kBlock - 1) / kBlock);
+        CK(launch_moments(ctx->opt.precision, ctx->pop((int)(ctx->step & 1)), ctx->d_reps() + r, R, z0, z1, nullptr,
+                          nullptr, ctx->d_mpart(), ctx->stream));
+        CK(launch_sum_partials(ctx->d_mpart(), nb, ctx->d_tot(), first ? 0 : 1, ctx->stream));
+        first = false;
+    }
+    double tot[4];
+    std::vector<double> acc(kAccStride);
+    CK(hipMemcpyAsync(tot, ctx->d_tot(), sizeof(tot), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipMemcpyAsync(acc.data(), ctx->d_acc() + (size_t)r * kAccStride, sizeof(double) * kAccStride,
+                      hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    std::memset(out, 0, sizeof(*out));
+    out->step = ctx->step;
+    out->nsamples = (int64_t)acc[kAccNsamp];
+    out->nonfinite = (int64_t)acc[kAccNonfinite];
+    out->mass = tot[0];
+    for (int a = 0; a < 3; ++a) out->momentum[a] = tot[1 + a];
+    for (int q = 0; q < kObs; ++q) {
+        out->sum_mean[q] = acc[kAccMean + q];
+        out->sum_meansq[q] = acc[kAccMeanSq + q];
+        out->sum_var[q] = acc[kAccVar + q];
+    }
+    for (int m = 0; m < kSpec; ++m)
+        for (int s = 0; s < kShells; ++s) out->spectrum[m][s] = acc[kAccSpec + m * kShells + s];
+    for (int s = 0; s < kShells; ++s) {
+        out->shell_n2[s] = kShellN2[s];
+        out->shell_count[s] = kShellCnt[s];
+    }
+    if (out->nonfinite > 0 || !std::isfinite(out->mass)) return GMF_EUNSTABLE;
+    return GMF_OK;
+}
+
+int gmf_reset_stats(gmf_ctx* ctx)
+{
+    int rc = check_ctx(ctx);
+    if (rc != GMF_OK) return rc;
+    DeviceGuard g(ctx->device);
+    CK(hipMemsetAsync(ctx->d_acc(), 0, sizeof(double) * kAccStride * ctx->nrep, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    return GMF_OK;
+}
+
+int gmf_get_populations(gmf_ctx* ctx, int32_t r, double* f)
+{
+    int rc = check_ctx(ctx);
+    if (rc != GMF_OK) return rc;
+    if (r < 0 || r >= ctx->nrep || !f) return GMF_EINVAL;
+    DeviceGuard g(ctx->device);
+    const RepDev& R = ctx->rdev[r];
+    const uint64_t plane = (uint64_t)R.nx * R.ny;
+    const uint32_t cp = chunk_planes(ctx, r);
+    double* st = reinterpret_cast<double*>(ctx->d_stage());
+    for (uint32_t z0 = 0; z0 < R.nz; z0 += cp) {
+        const uint32_t z1 = std::min(R.nz, z0 + cp);
+        const uint64_t cnt = plane * (z1 - z0);
+        CK(launch_gather(ctx->opt.precision, ctx->pop((int)(ctx->step & 1)), ctx->d_reps() + r, R, z0, z1, st,
+                         ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < Q; ++i)
+            CK(hipMemcpy(f + (uint64_t)i * R.n + plane * z0, st + (uint64_t)i * cnt, sizeof(double) * cnt,
+                         hipMemcpyDeviceToHost));
+    }
+    return GMF_OK;
+}
+
+int gmf_set_populations(gmf_ctx* ctx, int32_t r, const double* f)
+{
+    int rc = check_ctx(ctx);
+    if (rc != GMF_OK) return rc;
+    if (r < 0 || r >= ctx->nrep || !f) return GMF_EINVAL;
+    DeviceGuard g(ctx->device);
+    const RepDev& R = ctx->rdev[r];
+    const uint64_t plane = (uint64_t)R.nx * R.ny;
+    const uint32_t cp = chunk_planes(ctx, r);
+    double* st = reinterpret_cast<double*>(ctx->d_stage());
+    CK(hipStreamSynchronize(ctx->stream));
+    for (uint32_t z0 = 0; z0 < R.nz; z0 += cp) {
+        const uint32_t z1 = std::min(R.nz, z0 + cp);
+        const uint64_t cnt = plane * (z1 - z0);
+        for (int i = 0; i < Q; ++i)
+            CK(hipMemcpy(st + (uint64_t)i * cnt, f + (uint64_t)i * R.n + plane * z0, sizeof(double) * cnt,
+                         hipMemcpyHostToDevice));
+        CK(launch_scatter(ctx->opt.precision, ctx->pop((int)(ctx->step & 1)), ctx->d_reps() + r, R, z0, z1, st,
+                          ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+    }
+    return GMF_OK;
+}
+
+int gmf_get_nodes(gmf_ctx* ctx, int32_t r, const int64_t* nodes, int32_t count, double* f)
+{
+    int rc = check_ctx(ctx);
+    if (rc != GMF_OK) return rc;
+    if (r < 0 || r >= ctx->nrep || count < 0 || (count > 0 && (!nodes || !f))) return GMF_EINVAL;
+    const RepDev& R = ctx->rdev[r];
+    for (int32_t j = 0; j < count; ++j)
+        if (nodes[j] < 0 || (uint64_t)nodes[j] >= R.n) return GMF_EINVAL;
+    DeviceGuard g(ctx->device);
+    const size_t per = sizeof(int64_t) + sizeof(double) * Q;
+    // node list, alignment gap (< kAlign) and outputs must fit the staging area
+    const int32_t batch = (int32_t)std::min<size_t>((ctx->L.stage_bytes - kAlign) / per, 1u << 20);
+    char* st = ctx->d_stage();
+    for (int32_t j0 = 0; j0 < count; j0 += batch) {
+        const int32_t c = std::min(batch, count - j0);
+        int64_t* dn = reinterpret_cast<int64_t*>(st);
+        double* dout = reinterpret_cast<double*>(st + align_up(sizeof(int64_t) * (size_t)c));
+        CK(hipStreamSynchronize(ctx->stream));
+        CK(hipMemcpy(dn, nodes + j0, sizeof(int64_t) * c, hipMemcpyHostToDevice));
+        CK(launch_nodes(ctx->opt.precision, ctx->pop((int)(ctx->step & 1)), ctx->d_reps() + r, dn, c, dout,
+                        ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+        CK(hipMemcpy(f + (size_t)j0 * Q, dout, sizeof(double) * Q * c, hipMemcpyDeviceToHost));
+    }
+    return GMF_OK;
+}
+
+int gmf_get_step(gmf_ctx* ctx, int64_t* t)
+{
+    if (!ctx) return GMF_ESTATE;
+    if (!t) return GMF_EINVAL;
+    *t = ctx->step;
+    return GMF_OK;
+}
+
+int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int32_t* graphs)
+{
+    if (!ctx) return GMF_ESTATE;
+    if (nodes_per_thread) *nodes_per_thread = ctx->npt;
+    if (block) *block = kBlock;
+    if (graphs) *graphs = ctx->graph_steps;
+    return GMF_OK;
+}
+
+int gmf_noise_probe(uint64_t seed, int64_t t, uint32_t node0, int32_t count, int32_t precision, uint32_t* words,
+                    double* normals)
+{
+    if (count < 0 || (precision != GMF_FP64 && precision != GMF_FP32_SHIFTED)) return GMF_EINVAL;
+    if (count == 0) return GMF_OK;
+    if ((uint64_t)node0 + (uint64_t)count > (1ull << 32)) return GMF_EINVAL;
+    hipStream_t s = nullptr;
+    uint32_t* dw = nullptr;
+    double* dn = nullptr;
+    int rc = GMF_OK;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return GMF_EDEVICE;
+    if ((words && hipMalloc((void**)&dw, sizeof(uint32_t) * 24 * (size_t)count) != hipSuccess) ||
+        (normals && hipMalloc((void**)&dn, sizeof(double) * 23 * (size_t)count) != hipSuccess)) {
+        rc = GMF_ENOMEM;
+    } else if (launch_noise_probe(precision, seed, t, node0, count, dw, dn, s) != hipSuccess ||
+               hipStreamSynchronize(s) != hipSuccess) {
+        rc = GMF_EDEVICE;
+    } else {
+        if (words && hipMemcpy(words, dw, sizeof(uint32_t) * 24 * (size_t)count, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = GMF_EDEVICE;
+        if (normals && hipMemcpy(normals, dn, sizeof(double) * 23 * (size_t)count, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = GMF_EDEVICE;
+    }
+    if (dw) (void)hipFree(dw);
+    if (dn) (void)hipFree(dn);
+    (void)hipStreamDestroy(s);
+    return rc;
+}
+
+void gmf_destroy(gmf_ctx* ctx)
+{
+    if (!ctx) return;
+    DeviceGuard g(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto& gr : ctx->graphs) (void)hipGraphExecDestroy(gr.second);
+    if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char* gmf_strerror(int code)
+{
+    switch (code) {
+    case GMF_OK: return "success";
+    case GMF_EINVAL: return "invalid argument";
+    case GMF_ENOMEM: return "out of memory";
+    case GMF_EDEVICE: return "HIP device error (context poisoned)";
+    case GMF_ESTATE: return "invalid context";
+    case GMF_EUNSTABLE: return "non-finite density (numerical instability)";
+    default: return "unknown error";
+    }
+}
+
+}  // extern "C"

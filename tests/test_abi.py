@@ -1,0 +1,81 @@
+"""The C ABI library loads and exports what include/gmf.h declares; argument
+validation that needs no device (CPU only: no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2601_03806_amd as gmf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "gmf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gmf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("gmf_init", "gmf_step", "gmf_moments", "gmf_stats"):
+        assert required in names
+    assert set(names) == set(gmf.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = gmf.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(gmf.Replica) == 48
+    assert ctypes.sizeof(gmf.Options) == 32
+    # 3 int64 + 4 doubles + 3*10 doubles + 40 doubles + 16 int32
+    assert ctypes.sizeof(gmf.Stats) == 8 * 3 + 8 * 4 + 8 * 30 + 8 * 40 + 4 * 16
+
+
+def _ws(specs, **kw):
+    return gmf.workspace_bytes([gmf.ReplicaSpec(*s) for s in specs], **kw)
+
+
+def test_workspace_bytes_and_validation():
+    ok = _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)])
+    # two FP64 population buffers dominate
+    assert ok >= 2 * 27 * 8 * 16 ** 3
+    f32 = _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], precision=gmf.FP32_SHIFTED)
+    assert 2 * 27 * 4 * 16 ** 3 <= f32 < ok
+    # invalid replicas -> 0
+    assert _ws([(16, 16, 16, 1.0, 0.5, 1e-4, 1)]) == 0          # tau <= 1/2
+    assert _ws([(16, 16, 16, 1.0, float("nan"), 1e-4, 1)]) == 0
+    assert _ws([(0, 16, 16, 1.0, 1.0, 1e-4, 1)]) == 0           # empty box
+    assert _ws([(16, 16, 16, 0.0, 1.0, 1e-4, 1)]) == 0          # rho0 <= 0
+    assert _ws([(16, 16, 16, 1.0, 1.0, -1e-4, 1)]) == 0         # k_B T < 0
+    assert _ws([(1024, 1024, 1024, 1.0, 1.0, 1e-4, 1)]) == 0    # 32-bit offsets exceeded (FP64)
+    assert _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], precision=7) == 0
+    assert _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], sample_every=-1) == 0
+    assert _ws([(2048, 1024, 1, 1.0, 1.0, 1e-4, 1)], sample_every=10) == 0   # spectra LDS limit
+    # the 512^3 stress workload fits both precisions
+    assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)]) > 2 * 27 * 8 * 512 ** 3
+    assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)], precision=gmf.FP32_SHIFTED) > 0
+
+
+def test_init_rejects_before_touching_the_device():
+    lib = gmf.lib()
+    reps = gmf.make_replicas([gmf.ReplicaSpec(8, 8, 8, 1.0, 0.4, 1e-4, 1)])
+    opt = gmf.make_options()
+    h = ctypes.c_void_p()
+    assert lib.gmf_init(reps, 1, ctypes.byref(opt), None, 0, None, ctypes.byref(h)) == gmf.GMF_EINVAL
+    assert lib.gmf_init(reps, 0, ctypes.byref(opt), None, 0, None, ctypes.byref(h)) == gmf.GMF_EINVAL
+    good = gmf.make_replicas([gmf.ReplicaSpec(8, 8, 8, 1.0, 0.8, 1e-4, 1)])
+    need = lib.gmf_workspace_bytes(good, 1, ctypes.byref(opt))
+    # a caller workspace that is too small
+    assert lib.gmf_init(good, 1, ctypes.byref(opt), ctypes.c_void_p(256), need - 1, None,
+                        ctypes.byref(h)) == gmf.GMF_EINVAL
+    # NULL context
+    assert lib.gmf_step(None, 1) == gmf.GMF_ESTATE
+    assert lib.gmf_stats(None, 0, None) == gmf.GMF_ESTATE
+    assert lib.gmf_noise_probe(1, 0, 0, -1, 0, None, None) == gmf.GMF_EINVAL
+    assert gmf.strerror(gmf.GMF_EUNSTABLE).startswith("non-finite")
