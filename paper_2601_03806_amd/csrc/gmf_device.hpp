@@ -8,6 +8,16 @@
 // full-Hermite basis of Table II factorise over the three axes, which is what
 // the separable moment transforms in the step kernel use.  The host interface
 // converts to and from the documented canonical order (see gmf.h).
+//
+// Storage layout of one replica ("row-interleaved"): the 27 populations are
+// split into 27/G groups of G (G in {27, 9, 3, 1}, the largest for which a
+// group fits 32-bit byte offsets); inside a group, each x-row of the box keeps
+// its G population rows next to each other:
+//     element(p, x, y, z) = g N G + ((z ny + y) G + q) nx + x,
+// with slot s = 3 (3 (cy+1) + (cz+1)) + (cx+1), g = s / G, q = s % G.  The
+// populations that a node pulls from one neighbouring row then sit in one
+// contiguous block, and a wavefront's 27 stores land in a few DRAM pages
+// instead of 27 separate arrays.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,6 +41,9 @@ __host__ __device__ constexpr int tcx(int p) { return p / 9 - 1; }
 __host__ __device__ constexpr int tcy(int p) { return (p / 3) % 3 - 1; }
 __host__ __device__ constexpr int tcz(int p) { return p % 3 - 1; }
 __host__ __device__ constexpr int tindex(int cx, int cy, int cz) { return 9 * (cx + 1) + 3 * (cy + 1) + (cz + 1); }
+// storage slot of tensor-order population p: x-velocity fastest, so that the
+// three populations pulled from the same neighbouring row are adjacent
+__host__ __device__ constexpr int slot_of(int p) { return 3 * (p % 9) + p / 9; }
 
 // D1Q3 weight factor: w(c) = w1(cx) w1(cy) w1(cz), w1(0) = 2/3, w1(+-1) = 1/6
 __host__ __device__ constexpr double w1(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
@@ -68,12 +81,40 @@ struct RepDev {
     uint32_t dft_offset;      // offset (in complex values) of the replica's DFT partials
     uint32_t noise_on;        // 0 when k_BT = 0
     uint32_t noise_rho0;      // 1: rho0 instead of the local rho in the noise amplitudes
-    uint32_t pad0;
+    uint32_t grp;             // populations per storage group (27, 3 or 1)
+    uint64_t grp_elems;       // elements per storage group (n * grp)
+    uint32_t row_stride;      // elements between consecutive rows of a group (grp * nx)
+    uint32_t pad1;
     double rho0;
     double omega;             // 1 / tau
     double one_m_omega;       // 1 - omega
     double amp[8];            // noise amplitudes / sqrt(rho): groups of equal b_k (see host)
 };
+
+// Element offset (inside the replica block) of the start of population p's
+// row at (y, z) = (0, 0): uniform per population, added to the base pointer.
+// The step kernel instantiates the group size G at compile time.
+template <int G>
+__host__ __device__ inline uint64_t pop_base_offset_g(const RepDev& R, int p)
+{
+    const uint32_t s = (uint32_t)slot_of(p);
+    return (uint64_t)(s / G) * R.grp_elems + (uint64_t)(s % G) * R.nx;
+}
+__host__ __device__ inline uint64_t pop_base_offset(const RepDev& R, int p)
+{
+    const uint32_t s = (uint32_t)slot_of(p);
+    return (uint64_t)(s / R.grp) * R.grp_elems + (uint64_t)(s % R.grp) * R.nx;
+}
+// Element offset of row (y, z) inside a group (valid for every population).
+__host__ __device__ inline uint32_t row_offset(const RepDev& R, uint32_t y, uint32_t z)
+{
+    return (z * R.ny + y) * R.row_stride;
+}
+// Full element offset of population p at node (x, y, z).
+__host__ __device__ inline uint64_t pop_index(const RepDev& R, int p, uint32_t x, uint32_t y, uint32_t z)
+{
+    return pop_base_offset(R, p) + row_offset(R, y, z) + x;
+}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10: ten rounds of two 32x32->64 multiplies and xors, key bumped by
@@ -82,6 +123,12 @@ struct RepDev {
 struct U4 {
     uint32_t x, y, z, w;
 };
+
+// three-input xor in one VALU op (gfx950 v_bitop3_b32, truth table 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
 
 __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
 {
@@ -94,9 +141,9 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
         U4 o;
-        o.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+        o.x = xor3((uint32_t)(p1 >> 32), c.y, k0);
         o.y = (uint32_t)p1;
-        o.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        o.z = xor3((uint32_t)(p0 >> 32), c.w, k1);
         o.w = (uint32_t)p0;
         c = o;
     }

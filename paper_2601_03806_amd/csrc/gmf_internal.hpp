@@ -33,7 +33,8 @@ struct StepArgs {
 };
 
 // lattice kernels
-hipError_t launch_step(int precision, int collision, bool sample, int npt, const StepArgs& a,
+// grp: storage group size shared by every replica of the context (27, 3 or 1)
+hipError_t launch_step(int precision, int collision, bool sample, int grp, int npt, const StepArgs& a,
                        uint32_t nblocks, hipStream_t s);
 hipError_t launch_init(int precision, void* buf, const RepDev* rep_dev, const RepDev& rep, hipStream_t s);
 hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* partials, double* acc,

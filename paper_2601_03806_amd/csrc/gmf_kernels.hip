@@ -111,29 +111,103 @@ __device__ constexpr int kGhostGroup[17] = {2, 2, 2, 2, 2, 2, 3, 4, 4, 4, 5, 5, 
 // ---------------------------------------------------------------------------
 // The fused stream + collide step
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ const T* pop_ptr(const void* base, uint64_t off)
+// Population traffic goes through raw buffer instructions: one resource per
+// storage group (uniform), the population's row start as scalar offset and the
+// node's row/x offset as 32-bit vector offset, so no per-access 64-bit address
+// arithmetic is spent on the vector ALUs.  Every population value is read and
+// written exactly once per step: the accesses are marked nontemporal.
+constexpr int kNontemporal = 2;   // cache-policy bits of the buffer builtins on gfx950
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base)
 {
-    return reinterpret_cast<const T*>(base) + off;
+    // raw buffer: stride 0, 2^32 - 1 bytes addressable, gfx9 resource word 3
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, -1, 0x00020000);
 }
 
 template <typename T>
-__device__ __forceinline__ T ldg(const T* base, uint32_t idx)
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
 {
-    // 32-bit byte offset from a uniform base: lets the backend use the
-    // scalar-base + vector-offset addressing form
-    const uint32_t boff = idx * (uint32_t)sizeof(T);
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, kNontemporal));
+}
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kNontemporal));
+}
+
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, kNontemporal);
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double v)
+{
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, kNontemporal);
+}
+
+// resource of the storage group holding population p, and p's row-start offset in it (bytes)
+template <typename T, int G>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t group_rsrc(const void* rep_base, const RepDev& R, int p)
+{
+    const int g = slot_of(p) / G;
+    return make_rsrc(reinterpret_cast<const char*>(rep_base) + (uint64_t)g * R.grp_elems * sizeof(T));
+}
+template <typename T, int G>
+__device__ __forceinline__ uint32_t slot_soff(const RepDev& R, int p)
+{
+    return (uint32_t)(slot_of(p) % G) * R.nx * (uint32_t)sizeof(T);
 }
 
 template <typename T>
-__device__ __forceinline__ void stg(T* base, uint32_t idx, T v)
+__device__ __forceinline__ void stg_cached(T* base, uint32_t idx, T v)
 {
     const uint32_t boff = idx * (uint32_t)sizeof(T);
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
 }
 
-template <typename T, bool SHIFTED, int COLL, bool SAMPLE>
+// The replica record is read once per workgroup and pinned in scalar
+// registers: the compiler cannot otherwise prove that fields re-read after
+// the first stores are uniform, and buffer offsets must be scalar.
+__device__ __forceinline__ uint32_t sgpr(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t sgpr64(uint64_t v)
+{
+    return ((uint64_t)sgpr((uint32_t)(v >> 32)) << 32) | sgpr((uint32_t)v);
+}
+__device__ __forceinline__ double sgprf(double v) { return __builtin_bit_cast(double, sgpr64(__builtin_bit_cast(uint64_t, v))); }
+
+__device__ __forceinline__ RepDev uniform_rep(const RepDev& in)
+{
+    RepDev R;
+    R.pop_offset = sgpr64(in.pop_offset);
+    R.field_offset = sgpr64(in.field_offset);
+    R.nx = sgpr(in.nx);
+    R.ny = sgpr(in.ny);
+    R.nz = sgpr(in.nz);
+    R.n = sgpr(in.n);
+    R.divx = FastDiv{sgpr(in.divx.d), sgpr(in.divx.m), sgpr(in.divx.s)};
+    R.divy = FastDiv{sgpr(in.divy.d), sgpr(in.divy.m), sgpr(in.divy.s)};
+    R.block_begin = sgpr(in.block_begin);
+    R.nblocks = sgpr(in.nblocks);
+    R.key0 = sgpr(in.key0);
+    R.key1 = sgpr(in.key1);
+    R.dft_offset = sgpr(in.dft_offset);
+    R.noise_on = sgpr(in.noise_on);
+    R.noise_rho0 = sgpr(in.noise_rho0);
+    R.grp = sgpr(in.grp);
+    R.grp_elems = sgpr64(in.grp_elems);
+    R.row_stride = sgpr(in.row_stride);
+    R.pad1 = 0;
+    R.rho0 = sgprf(in.rho0);
+    R.omega = sgprf(in.omega);
+    R.one_m_omega = sgprf(in.one_m_omega);
+#pragma unroll
+    for (int g = 0; g < 8; ++g) R.amp[g] = sgprf(in.amp[g]);
+    return R;
+}
+
+template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int G>
 __device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, uint32_t n, uint64_t t,
                                             double* acc)
 {
@@ -142,25 +216,30 @@ __device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, 
     const uint32_t x = n - yz * nx;
     const uint32_t z = fdiv(yz, R.divy);
     const uint32_t y = yz - z * ny;
-    const uint32_t plane = nx * ny;
 
     // pull: f_p(x) = f*_p(x - c_p); index 0/1/2 <-> c = -1/0/+1
-    uint32_t xs[3], ys[3], zs[3];
+    uint32_t xs[3], yv[3], zv[3];
     xs[0] = (x + 1 == nx) ? 0u : x + 1;
     xs[1] = x;
     xs[2] = (x == 0) ? nx - 1 : x - 1;
-    const uint32_t yp = (y + 1 == ny) ? 0u : y + 1, ym = (y == 0) ? ny - 1 : y - 1;
-    const uint32_t zp = (z + 1 == nz) ? 0u : z + 1, zm = (z == 0) ? nz - 1 : z - 1;
-    ys[0] = yp * nx; ys[1] = y * nx; ys[2] = ym * nx;
-    zs[0] = zp * plane; zs[1] = z * plane; zs[2] = zm * plane;
+    yv[0] = (y + 1 == ny) ? 0u : y + 1;
+    yv[1] = y;
+    yv[2] = (y == 0) ? ny - 1 : y - 1;
+    zv[0] = (z + 1 == nz) ? 0u : z + 1;
+    zv[1] = z;
+    zv[2] = (z == 0) ? nz - 1 : z - 1;
+    // byte offsets: source row (y - cy, z - cz) at index 3*cyi + czi, source x
+    uint32_t rows[9], xb[3];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) rows[q] = row_offset(R, yv[q / 3], zv[q % 3]) * (uint32_t)sizeof(T);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) xb[q] = xs[q] * (uint32_t)sizeof(T);
 
-    const T* src = pop_ptr<T>(a.src, R.pop_offset);
+    const T* src = reinterpret_cast<const T*>(a.src) + R.pop_offset;
     T f[Q];
 #pragma unroll
-    for (int p = 0; p < Q; ++p) {
-        const uint32_t idx = zs[p % 3] + ys[(p / 3) % 3] + xs[p / 9];
-        f[p] = ldg(src + (uint64_t)p * N, idx);
-    }
+    for (int p = 0; p < Q; ++p)
+        f[p] = bload<T>(group_rsrc<T, G>(src, R, p), rows[p % 9] + xb[p / 9], slot_soff<T, G>(R, p));
 
     // noise words do not depend on the populations: issue them while the loads fly
     T r[23];
@@ -217,20 +296,21 @@ __device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, 
     }
 
     T* dst = reinterpret_cast<T*>(a.dst) + R.pop_offset;
+    const uint32_t self = rows[4] + xb[1];
 #pragma unroll
-    for (int p = 0; p < Q; ++p) stg(dst + (uint64_t)p * N, n, F[p]);
+    for (int p = 0; p < Q; ++p) bstore(group_rsrc<T, G>(dst, R, p), self, slot_soff<T, G>(R, p), F[p]);
 
     if (SAMPLE) {
         const T drho = SHIFTED ? h.s0 : h.s0 - rho0;
         const T pdiag = SHIFTED ? (h.pxx + h.pyy + h.pzz) : (h.pxx + h.pyy + h.pzz - T(3) * cs2 * rho0);
         const T poff = h.pxy + h.pxz + h.pyz;
         T* fl = reinterpret_cast<T*>(a.fields) + R.field_offset;
-        stg(fl + 0ull * N, n, drho);
-        stg(fl + 1ull * N, n, h.jx);
-        stg(fl + 2ull * N, n, h.jy);
-        stg(fl + 3ull * N, n, h.jz);
-        stg(fl + 4ull * N, n, pdiag);
-        stg(fl + 5ull * N, n, poff);
+        stg_cached(fl + 0ull * N, n, drho);
+        stg_cached(fl + 1ull * N, n, h.jx);
+        stg_cached(fl + 2ull * N, n, h.jy);
+        stg_cached(fl + 3ull * N, n, h.jz);
+        stg_cached(fl + 4ull * N, n, pdiag);
+        stg_cached(fl + 5ull * N, n, poff);
         double o[kObs];
         o[0] = (double)drho;
         o[1] = (double)h.jx; o[2] = (double)h.jy; o[3] = (double)h.jz;
@@ -272,13 +352,13 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* out)
     }
 }
 
-template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int NPT>
+template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int NPT, int G>
 __global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a)
 {
     const uint32_t blk = blockIdx.x;
-    const int r = a.blk2rep ? (int)a.blk2rep[blk] : 0;
-    const RepDev& R = a.reps[r];
-    const uint64_t t = (uint64_t)(a.step_base + (a.d_step ? *a.d_step : 0));
+    const int r = a.blk2rep ? (int)sgpr(a.blk2rep[blk]) : 0;
+    const RepDev R = uniform_rep(a.reps[r]);
+    const uint64_t t = sgpr64((uint64_t)(a.step_base + (a.d_step ? *a.d_step : 0)));
     const uint32_t base = (blk - R.block_begin) * (uint32_t)(kBlock * NPT) + threadIdx.x;
     double acc[2 * kObs + 1];
     if (SAMPLE) {
@@ -288,38 +368,49 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a)
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const uint32_t n = base + (uint32_t)(k * kBlock);
-        if (n < R.n) node_update<T, SHIFTED, COLL, SAMPLE>(a, R, n, t, acc);
+        if (n < R.n) node_update<T, SHIFTED, COLL, SAMPLE, G>(a, R, n, t, acc);
     }
     if (SAMPLE) block_sum_store<2 * kObs + 1>(acc, a.partials + (size_t)blk * kPartialStride);
 }
 
-template <typename T, bool SHIFTED, int COLL, bool SAMPLE>
+template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int G>
 static hipError_t launch_step_npt(int npt, const StepArgs& a, uint32_t nblocks, hipStream_t s)
 {
     switch (npt) {
-    case 1: step_kernel<T, SHIFTED, COLL, SAMPLE, 1><<<nblocks, kBlock, 0, s>>>(a); break;
-    case 2: step_kernel<T, SHIFTED, COLL, SAMPLE, 2><<<nblocks, kBlock, 0, s>>>(a); break;
-    case 4: step_kernel<T, SHIFTED, COLL, SAMPLE, 4><<<nblocks, kBlock, 0, s>>>(a); break;
+    case 1: step_kernel<T, SHIFTED, COLL, SAMPLE, 1, G><<<nblocks, kBlock, 0, s>>>(a); break;
+    case 2: step_kernel<T, SHIFTED, COLL, SAMPLE, 2, G><<<nblocks, kBlock, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <typename T, bool SHIFTED>
-static hipError_t launch_step_t(int collision, bool sample, int npt, const StepArgs& a, uint32_t nb, hipStream_t s)
+template <typename T, bool SHIFTED, int COLL, bool SAMPLE>
+static hipError_t launch_step_grp(int grp, int npt, const StepArgs& a, uint32_t nb, hipStream_t s)
 {
-    if (collision == kGMF)
-        return sample ? launch_step_npt<T, SHIFTED, kGMF, true>(npt, a, nb, s)
-                      : launch_step_npt<T, SHIFTED, kGMF, false>(npt, a, nb, s);
-    return sample ? launch_step_npt<T, SHIFTED, kBGK, true>(npt, a, nb, s)
-                  : launch_step_npt<T, SHIFTED, kBGK, false>(npt, a, nb, s);
+    switch (grp) {
+    case 27: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, 27>(npt, a, nb, s);
+    case 3: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, 3>(npt, a, nb, s);
+    case 1: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, 1>(npt, a, nb, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
-hipError_t launch_step(int precision, int collision, bool sample, int npt, const StepArgs& a, uint32_t nblocks,
-                       hipStream_t s)
+template <typename T, bool SHIFTED>
+static hipError_t launch_step_t(int collision, bool sample, int grp, int npt, const StepArgs& a, uint32_t nb,
+                                hipStream_t s)
 {
-    if (precision == kFP64) return launch_step_t<double, false>(collision, sample, npt, a, nblocks, s);
-    return launch_step_t<float, true>(collision, sample, npt, a, nblocks, s);
+    if (collision == kGMF)
+        return sample ? launch_step_grp<T, SHIFTED, kGMF, true>(grp, npt, a, nb, s)
+                      : launch_step_grp<T, SHIFTED, kGMF, false>(grp, npt, a, nb, s);
+    return sample ? launch_step_grp<T, SHIFTED, kBGK, true>(grp, npt, a, nb, s)
+                  : launch_step_grp<T, SHIFTED, kBGK, false>(grp, npt, a, nb, s);
+}
+
+hipError_t launch_step(int precision, int collision, bool sample, int grp, int npt, const StepArgs& a,
+                       uint32_t nblocks, hipStream_t s)
+{
+    if (precision == kFP64) return launch_step_t<double, false>(collision, sample, grp, npt, a, nblocks, s);
+    return launch_step_t<float, true>(collision, sample, grp, npt, a, nblocks, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -331,9 +422,10 @@ __global__ __launch_bounds__(kBlock) void init_kernel(T* buf, const RepDev* rep)
     const RepDev& R = *rep;
     const uint32_t n = blockIdx.x * (uint32_t)kBlock + threadIdx.x;
     if (n >= R.n) return;
+    const uint32_t x = n % R.nx, y = (n / R.nx) % R.ny, z = n / (R.nx * R.ny);
     T* b = buf + R.pop_offset;
 #pragma unroll
-    for (int p = 0; p < Q; ++p) b[(uint64_t)p * R.n + n] = SHIFTED ? T(0) : (T)(tweight(p) * R.rho0);
+    for (int p = 0; p < Q; ++p) b[pop_index(R, p, x, y, z)] = SHIFTED ? T(0) : (T)(tweight(p) * R.rho0);
 }
 
 hipError_t launch_init(int precision, void* buf, const RepDev* rep_dev, const RepDev& rep, hipStream_t s)
@@ -629,8 +721,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(const T* src, const RepD
         const uint32_t xs = (x + R.nx - tcx(p)) % R.nx;
         const uint32_t ys = (y + R.ny - tcy(p)) % R.ny;
         const uint32_t zs = (z + R.nz - tcz(p)) % R.nz;
-        const uint64_t node = xs + (uint64_t)R.nx * (ys + (uint64_t)R.ny * zs);
-        double v = (double)s[(uint64_t)p * R.n + node];
+        double v = (double)s[pop_index(R, p, xs, ys, zs)];
         if (SHIFTED) v += tweight(p) * R.rho0;
         out[(uint64_t)i * cnt + idx] = v;
     }
@@ -654,10 +745,9 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(T* dst, const RepDev* r
         const uint32_t xs = (x + R.nx - tcx(p)) % R.nx;
         const uint32_t ys = (y + R.ny - tcy(p)) % R.ny;
         const uint32_t zs = (z + R.nz - tcz(p)) % R.nz;
-        const uint64_t node = xs + (uint64_t)R.nx * (ys + (uint64_t)R.ny * zs);
         double v = in[(uint64_t)i * cnt + idx];
         if (SHIFTED) v -= tweight(p) * R.rho0;
-        d[(uint64_t)p * R.n + node] = (T)v;
+        d[pop_index(R, p, xs, ys, zs)] = (T)v;
     }
 }
 
@@ -681,8 +771,7 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(const T* src, const Rep
             const uint32_t xs = (x + R.nx - tcx(p)) % R.nx;
             const uint32_t ys = (y + R.ny - tcy(p)) % R.ny;
             const uint32_t zs = (z + R.nz - tcz(p)) % R.nz;
-            const uint64_t node = xs + (uint64_t)R.nx * (ys + (uint64_t)R.ny * zs);
-            double fv = (double)s[(uint64_t)p * R.n + node];
+            double fv = (double)s[pop_index(R, p, xs, ys, zs)];
             if (SHIFTED) fv += tweight(p) * R.rho0;
             rho += fv;
             jx += fv * tcx(p);
@@ -729,8 +818,7 @@ __global__ __launch_bounds__(kBlock) void nodes_kernel(const T* src, const RepDe
         const uint32_t xs = (x + R.nx - tcx(p)) % R.nx;
         const uint32_t ys = (y + R.ny - tcy(p)) % R.ny;
         const uint32_t zs = (z + R.nz - tcz(p)) % R.nz;
-        const uint64_t node = xs + (uint64_t)R.nx * (ys + (uint64_t)R.ny * zs);
-        double v = (double)s[(uint64_t)p * R.n + node];
+        double v = (double)s[pop_index(R, p, xs, ys, zs)];
         if (SHIFTED) v += tweight(p) * R.rho0;
         out[(size_t)j * Q + i] = v;
     }

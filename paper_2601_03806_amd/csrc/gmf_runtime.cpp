@@ -166,6 +166,7 @@ struct gmf_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int npt = kDefaultNpt;
+    int grp = 27;                  // storage group size (see gmf_device.hpp)
     uint32_t nblocks = 0;          // lattice grid for the current npt
     int graph_steps = 0;           // 0: direct launches
     int period = 2;                // step pattern period (A/B parity, sampling)
@@ -246,7 +247,7 @@ int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
     a.fields = ctx->d_fields();
     a.partials = ctx->d_partials();
     const bool sample = sampling_step(ctx, t);
-    CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, ctx->npt, a, ctx->nblocks, ctx->stream));
+    CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, ctx->grp, ctx->npt, a, ctx->nblocks, ctx->stream));
     if (sample) {
         CK(launch_stats_reduce(ctx->d_reps(), ctx->nrep, ctx->d_partials(), ctx->d_acc(), ctx->stream));
         CK(launch_dft(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_plane2rep(), ctx->L.total_planes,
@@ -331,7 +332,7 @@ int autotune(gmf_ctx* ctx)
             fclose(fh);
         }
     }
-    const int cand[3] = {1, 2, 4};
+    const int cand[2] = {1, 2};
     hipEvent_t e0, e1;
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
@@ -350,10 +351,10 @@ int autotune(gmf_ctx* ctx)
         a.step_base = ctx->step;
         a.fields = nullptr;
         a.partials = nullptr;
-        CK(launch_step(ctx->opt.precision, ctx->opt.collision, false, c, a, ctx->nblocks, ctx->stream));
+        CK(launch_step(ctx->opt.precision, ctx->opt.collision, false, ctx->grp, c, a, ctx->nblocks, ctx->stream));
         CK(hipEventRecord(e0, ctx->stream));
         for (int i = 0; i < reps; ++i)
-            CK(launch_step(ctx->opt.precision, ctx->opt.collision, false, c, a, ctx->nblocks, ctx->stream));
+            CK(launch_step(ctx->opt.precision, ctx->opt.collision, false, ctx->grp, c, a, ctx->nblocks, ctx->stream));
         CK(hipEventRecord(e1, ctx->stream));
         CK(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -439,6 +440,20 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         ctx->own_stream = true;
     }
 
+    // storage group size: the largest of 27, 3, 1 whose byte offsets fit 32
+    // bits in every replica (one value per context: the step kernel is
+    // instantiated for it)
+    {
+        const uint64_t es = opt.precision == GMF_FP32_SHIFTED ? 4 : 8;
+        uint64_t nmax = 0;
+        for (int r = 0; r < nrep; ++r) nmax = std::max<uint64_t>(nmax, (uint64_t)reps[r].nx * reps[r].ny * reps[r].nz);
+        ctx->grp = 1;
+        for (int gsz : {27, 3})
+            if (nmax * (uint64_t)gsz * es < (1ull << 32)) {
+                ctx->grp = gsz;
+                break;
+            }
+    }
     // replica records
     uint64_t pop_off = 0, field_off = 0;
     uint32_t dft_off = 0;
@@ -452,6 +467,9 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         R.nz = (uint32_t)in.nz;
         R.n = R.nx * R.ny * R.nz;
         R.divx = make_fastdiv(R.nx);
+        R.grp = (uint32_t)ctx->grp;
+        R.grp_elems = (uint64_t)R.n * R.grp;
+        R.row_stride = R.grp * R.nx;
         R.divy = make_fastdiv(R.ny);
         R.pop_offset = pop_off;
         R.field_offset = field_off;
