@@ -99,7 +99,30 @@ def run_gpu(args, torch, gmf, wl):
     return out
 
 
-def cpu_baseline(target_seconds=12.0):
+def copy_probe(torch, gmf, gbytes=1.812, reps=20):
+    """The library's streaming copy of one 256^3 FP32 population buffer: the
+    practical bandwidth ceiling, and the reference that scales the rocprofv3
+    FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    n = (int(gbytes * 1e9) // 16) * 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        gmf.copy_probe(a.data_ptr(), b.data_ptr(), 4 * n, s)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        gmf.copy_probe(a.data_ptr(), b.data_ptr(), 4 * n, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    return {"bytes_read_plus_written": 2 * 4 * n, "seconds": sec, "gbs": 2 * 4 * n / sec / 1e9}
+
+
+def cpu_baseline(target_seconds=15.0):
     import oracle
     L = 16
     p = oracle.params(L, rho0=1.0, tau=1.0, kbt=1e-4, seed=1)
@@ -124,6 +147,8 @@ def main():
     ap.add_argument("--tune", type=int, default=0)
     ap.add_argument("--skip-extra", action="store_true", help="only the FP32 headline (profiling runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only time a plain device copy of one population buffer (bandwidth reference)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (replicas and slabs would shard "
@@ -139,6 +164,9 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
     gmf.lib()   # fail loudly if the HIP library is missing
+    if args.copy_probe:
+        print(json.dumps({"copy_probe": copy_probe(torch, gmf)}), flush=True)
+        return
 
     res = run_gpu(args, torch, gmf, wl)
     r32 = res["fp32"]
@@ -161,7 +189,7 @@ def main():
         "data": "synthetic (equilibrium fluid at rest, rho0=1, Philox noise)",
         "config": {"workload": "d3q27_256cube_fp32_tau0.8", "lattice": [256, 256, 256], "rho0": 1.0,
                    "tau": 0.8, "kbt": 1e-4, "seed": 1, "precision": "fp32_shifted",
-                   "layout": "SoA A/B pull", "kernel_config": r32["config"]},
+                   "layout": "row-interleaved populations, A/B pull", "kernel_config": r32["config"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic("step_fp32_256", r32["nodes"])},

@@ -182,8 +182,18 @@ int gmf_noise_probe(uint64_t seed, int64_t t, uint32_t node0, int32_t count, int
                     uint32_t* words, double* normals);
 
 /* Kernel configuration in use (for reports): nodes per thread, threads per
- * block, and 1 if the step loop runs through HIP graphs. */
-int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int32_t* graphs);
+ * workgroup, steps per captured HIP graph (0: direct launches), and the
+ * addressing mode of the step kernel (0: plane-uniform rows of 27 populations;
+ * 27, 3, 1: per-node addressing with storage groups of that many populations).
+ * Any output pointer may be NULL. */
+int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int32_t* graphs, int32_t* addressing);
+
+/* Bandwidth reference: enqueue one plain streaming copy of `bytes` (a positive
+ * multiple of 16) from device buffer src to device buffer dst (both 16-byte
+ * aligned, caller-owned, not overlapping) on hip_stream (NULL: the legacy
+ * stream).  Asynchronous.  The measured rate of this copy is the practical HBM
+ * ceiling that the step kernel's bandwidth is compared with. */
+int gmf_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream);
 
 /* Release the context and everything the library allocated for it. */
 void gmf_destroy(gmf_ctx* ctx);

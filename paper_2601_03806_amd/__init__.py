@@ -37,7 +37,7 @@ Q = 27
 EXPORTED = (
     "gmf_workspace_bytes", "gmf_init", "gmf_step", "gmf_moments", "gmf_stats", "gmf_reset_stats",
     "gmf_get_populations", "gmf_set_populations", "gmf_get_nodes", "gmf_get_step", "gmf_noise_probe",
-    "gmf_get_config", "gmf_destroy", "gmf_strerror",
+    "gmf_get_config", "gmf_copy_probe", "gmf_destroy", "gmf_strerror",
 )
 
 
@@ -99,7 +99,9 @@ def lib() -> ctypes.CDLL:
         L.gmf_noise_probe.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32), dp]
         L.gmf_get_config.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                     ctypes.POINTER(ctypes.c_int32)]
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.gmf_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.gmf_copy_probe.restype = ctypes.c_int
         L.gmf_destroy.argtypes = [vp]
         L.gmf_destroy.restype = None
         L.gmf_strerror.argtypes = [ctypes.c_int]
@@ -170,6 +172,12 @@ def noise_probe(seed: int, step: int, node0: int, count: int, precision: int = F
     return words.reshape(count, 6, 4), normals.reshape(count, 23)
 
 
+def copy_probe(src_ptr: int, dst_ptr: int, nbytes: int, stream=None):
+    """Enqueue the library's streaming copy (bandwidth reference) on a torch stream."""
+    sp = None if stream is None else int(stream.cuda_stream)
+    _check(lib().gmf_copy_probe(src_ptr, dst_ptr, nbytes, sp), "gmf_copy_probe")
+
+
 class Context:
     """A set of replicas advanced together by the library (one C context).
 
@@ -231,9 +239,11 @@ class Context:
         return v.value
 
     def config(self):
-        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().gmf_get_config(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "gmf_get_config")
-        return {"nodes_per_thread": a.value, "block": b.value, "graph_steps": c.value}
+        a, b, c, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().gmf_get_config(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)),
+               "gmf_get_config")
+        return {"nodes_per_thread": a.value, "block": b.value, "graph_steps": c.value,
+                "addressing": "plane" if d.value == 0 else f"group{d.value}"}
 
     # data ------------------------------------------------------------------
     def moments(self, r: int = 0):

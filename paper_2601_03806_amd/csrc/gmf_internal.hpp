@@ -33,7 +33,8 @@ struct StepArgs {
 };
 
 // lattice kernels
-// grp: storage group size shared by every replica of the context (27, 3 or 1)
+// grp: addressing mode shared by every replica of the context: 0 (plane-uniform,
+// storage groups of 27) or the storage group size 27, 3 or 1 (per-node addressing)
 hipError_t launch_step(int precision, int collision, bool sample, int grp, int npt, const StepArgs& a,
                        uint32_t nblocks, hipStream_t s);
 hipError_t launch_init(int precision, void* buf, const RepDev* rep_dev, const RepDev& rep, hipStream_t s);
@@ -59,6 +60,8 @@ hipError_t launch_nodes(int precision, const void* src, const RepDev* rep_dev, c
                         int32_t count, double* out, hipStream_t s);
 hipError_t launch_noise_probe(int precision, uint64_t seed, int64_t t, uint32_t node0, int32_t count,
                               uint32_t* words, double* normals, hipStream_t s);
+
+hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 
 // canonical velocity order of the interface -> internal tensor order
 void canonical_to_tensor(int out[Q]);

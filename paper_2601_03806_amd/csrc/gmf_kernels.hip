@@ -15,6 +15,8 @@
 // h0 = 1, h1 = c, h2 = c^2 - 1/3).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "gmf_device.hpp"
 #include "gmf_internal.hpp"
 
@@ -207,15 +209,32 @@ __device__ __forceinline__ RepDev uniform_rep(const RepDev& in)
     return R;
 }
 
+// Addressing modes of the step kernel:
+//   G = 27, 3, 1  per-node addressing; population groups of G (see gmf_device.hpp),
+//                 byte offsets inside a group must fit 32 bits;
+//   G = kPlane    every workgroup lies in one z plane (n_x n_y a multiple of the
+//                 nodes per workgroup); storage groups of 27, the three source
+//                 planes are uniform and get their own 64-bit scalar base, so only
+//                 a plane (n_y 27 n_x values) must fit 32-bit offsets.
+constexpr int kPlane = 0;
+
 template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int G>
-__device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, uint32_t n, uint64_t t,
-                                            double* acc)
+__device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, uint32_t n, uint32_t zplane,
+                                            uint64_t t, double* acc)
 {
     const uint32_t nx = R.nx, ny = R.ny, nz = R.nz, N = R.n;
-    const uint32_t yz = fdiv(n, R.divx);
-    const uint32_t x = n - yz * nx;
-    const uint32_t z = fdiv(yz, R.divy);
-    const uint32_t y = yz - z * ny;
+    uint32_t x, y, z;
+    if constexpr (G == kPlane) {
+        z = zplane;
+        const uint32_t local = n - z * (nx * ny);
+        y = fdiv(local, R.divx);
+        x = local - y * nx;
+    } else {
+        const uint32_t yz = fdiv(n, R.divx);
+        x = n - yz * nx;
+        z = fdiv(yz, R.divy);
+        y = yz - z * ny;
+    }
 
     // pull: f_p(x) = f*_p(x - c_p); index 0/1/2 <-> c = -1/0/+1
     uint32_t xs[3], yv[3], zv[3];
@@ -228,18 +247,39 @@ __device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, 
     zv[0] = (z + 1 == nz) ? 0u : z + 1;
     zv[1] = z;
     zv[2] = (z == 0) ? nz - 1 : z - 1;
-    // byte offsets: source row (y - cy, z - cz) at index 3*cyi + czi, source x
-    uint32_t rows[9], xb[3];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) rows[q] = row_offset(R, yv[q / 3], zv[q % 3]) * (uint32_t)sizeof(T);
+    uint32_t xb[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) xb[q] = xs[q] * (uint32_t)sizeof(T);
 
     const T* src = reinterpret_cast<const T*>(a.src) + R.pop_offset;
+    T* dst = reinterpret_cast<T*>(a.dst) + R.pop_offset;
     T f[Q];
+    uint32_t self;
+    __amdgpu_buffer_rsrc_t wr;   // plane mode: resource of the node's own plane
+    if constexpr (G == kPlane) {
+        // uniform source planes z - cz, per-node source rows y - cy (bytes inside a plane)
+        const uint64_t plane_elems = (uint64_t)ny * R.row_stride;
+        __amdgpu_buffer_rsrc_t rp[3];
 #pragma unroll
-    for (int p = 0; p < Q; ++p)
-        f[p] = bload<T>(group_rsrc<T, G>(src, R, p), rows[p % 9] + xb[p / 9], slot_soff<T, G>(R, p));
+        for (int q = 0; q < 3; ++q) rp[q] = make_rsrc(src + (uint64_t)zv[q] * plane_elems);
+        uint32_t ry[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) ry[q] = yv[q] * R.row_stride * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int p = 0; p < Q; ++p)
+            f[p] = bload<T>(rp[p % 3], ry[(p / 3) % 3] + xb[p / 9], slot_soff<T, 27>(R, p));
+        self = ry[1] + xb[1];
+        wr = make_rsrc(dst + (uint64_t)z * plane_elems);
+    } else {
+        // byte offsets: source row (y - cy, z - cz) at index 3*cyi + czi
+        uint32_t rows[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) rows[q] = row_offset(R, yv[q / 3], zv[q % 3]) * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int p = 0; p < Q; ++p)
+            f[p] = bload<T>(group_rsrc<T, G>(src, R, p), rows[p % 9] + xb[p / 9], slot_soff<T, G>(R, p));
+        self = rows[4] + xb[1];
+    }
 
     // noise words do not depend on the populations: issue them while the loads fly
     T r[23];
@@ -295,10 +335,13 @@ __device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, 
         for (int p = 0; p < Q; ++p) F[p] += omm * f[p];
     }
 
-    T* dst = reinterpret_cast<T*>(a.dst) + R.pop_offset;
-    const uint32_t self = rows[4] + xb[1];
+    if constexpr (G == kPlane) {
 #pragma unroll
-    for (int p = 0; p < Q; ++p) bstore(group_rsrc<T, G>(dst, R, p), self, slot_soff<T, G>(R, p), F[p]);
+        for (int p = 0; p < Q; ++p) bstore(wr, self, slot_soff<T, 27>(R, p), F[p]);
+    } else {
+#pragma unroll
+        for (int p = 0; p < Q; ++p) bstore(group_rsrc<T, G>(dst, R, p), self, slot_soff<T, G>(R, p), F[p]);
+    }
 
     if (SAMPLE) {
         const T drho = SHIFTED ? h.s0 : h.s0 - rho0;
@@ -359,7 +402,10 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a)
     const int r = a.blk2rep ? (int)sgpr(a.blk2rep[blk]) : 0;
     const RepDev R = uniform_rep(a.reps[r]);
     const uint64_t t = sgpr64((uint64_t)(a.step_base + (a.d_step ? *a.d_step : 0)));
-    const uint32_t base = (blk - R.block_begin) * (uint32_t)(kBlock * NPT) + threadIdx.x;
+    const uint32_t first = (blk - R.block_begin) * (uint32_t)(kBlock * NPT);
+    const uint32_t base = first + threadIdx.x;
+    // plane mode: the whole workgroup lies in z plane first / (nx ny)
+    const uint32_t zplane = G == kPlane ? fdiv(fdiv(first, R.divx), R.divy) : 0u;
     double acc[2 * kObs + 1];
     if (SAMPLE) {
 #pragma unroll
@@ -368,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a)
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const uint32_t n = base + (uint32_t)(k * kBlock);
-        if (n < R.n) node_update<T, SHIFTED, COLL, SAMPLE, G>(a, R, n, t, acc);
+        if (n < R.n) node_update<T, SHIFTED, COLL, SAMPLE, G>(a, R, n, zplane, t, acc);
     }
     if (SAMPLE) block_sum_store<2 * kObs + 1>(acc, a.partials + (size_t)blk * kPartialStride);
 }
@@ -388,6 +434,7 @@ template <typename T, bool SHIFTED, int COLL, bool SAMPLE>
 static hipError_t launch_step_grp(int grp, int npt, const StepArgs& a, uint32_t nb, hipStream_t s)
 {
     switch (grp) {
+    case kPlane: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, kPlane>(npt, a, nb, s);
     case 27: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, 27>(npt, a, nb, s);
     case 3: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, 3>(npt, a, nb, s);
     case 1: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, 1>(npt, a, nb, s);
@@ -914,6 +961,26 @@ hipError_t launch_noise_probe(int precision, uint64_t seed, int64_t t, uint32_t 
         noise_probe_kernel<double><<<g, kBlock, 0, s>>>(k0, k1, t, node0, count, words, normals);
     else
         noise_probe_kernel<float><<<g, kBlock, 0, s>>>(k0, k1, t, node0, count, words, normals);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Streaming copy (16-byte accesses, grid-stride): the practical bandwidth
+// reference the step kernel is compared with.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                      uint64_t n4)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += stride) dst[i] = src[i];
+}
+
+hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s)
+{
+    const uint64_t n4 = bytes / 16;
+    const uint64_t want = (n4 + kBlock - 1) / kBlock;
+    const uint32_t g = (uint32_t)std::min<uint64_t>(want, 1u << 20);
+    copy_kernel<<<g, kBlock, 0, s>>>(reinterpret_cast<const float4*>(src), reinterpret_cast<float4*>(dst), n4);
     return hipGetLastError();
 }
 

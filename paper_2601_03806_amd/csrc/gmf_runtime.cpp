@@ -51,6 +51,33 @@ struct Layout {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// Addressing modes of the step kernel (see gmf_kernels.hip) that fit a set of
+// replicas: per-node addressing with storage groups of 27, 3 or 1 populations
+// when the group's byte offsets fit 32 bits in every replica, and plane-uniform
+// addressing (0) when every z plane is a whole number of workgroups of
+// kBlock * npt nodes.
+bool mode_fits(const gmf_replica* reps, int32_t nrep, uint64_t es, int mode, int npt)
+{
+    for (int r = 0; r < nrep; ++r) {
+        const uint64_t pl = (uint64_t)reps[r].nx * reps[r].ny;
+        if (mode == 0) {
+            if (pl % ((uint64_t)kBlock * npt) != 0) return false;
+        } else if (pl * reps[r].nz * (uint64_t)mode * es >= (1ull << 32)) {
+            return false;
+        }
+    }
+    return true;
+}
+
+// Default mode: groups of 27 when they fit, else plane-uniform, else 3, else 1;
+// -1 when none fits.
+int choose_mode(const gmf_replica* reps, int32_t nrep, uint64_t es, int npt)
+{
+    for (int m : {27, 0, 3, 1})
+        if (mode_fits(reps, nrep, es, m, npt)) return m;
+    return -1;
+}
+
 int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
 {
     if (!reps || nrep < 1 || nrep > 65535) return GMF_EINVAL;
@@ -67,13 +94,14 @@ int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         const gmf_replica& R = reps[r];
         if (R.nx < 1 || R.ny < 1 || R.nz < 1 || R.reserved != 0) return GMF_EINVAL;
         const uint64_t n = (uint64_t)R.nx * R.ny * R.nz;
-        // 32-bit node indices and 32-bit byte offsets inside one population array
-        if (n >= (1ull << 31) || n * es >= (1ull << 32)) return GMF_EINVAL;
+        // 32-bit node indices; one z plane of 27 population rows within 32-bit byte offsets
+        if (n >= (1ull << 31) || (uint64_t)R.nx * R.ny * Q * es >= (1ull << 32)) return GMF_EINVAL;
         if (!finite_pos(R.rho0) || !std::isfinite(R.tau) || !(R.tau > 0.5)) return GMF_EINVAL;
         if (!std::isfinite(R.kbt) || R.kbt < 0.0) return GMF_EINVAL;
         // the spectra keep two twiddle tables and one row of partial sums per y in LDS
         if (sampling && 2 * (uint64_t)R.nx + 10 * (uint64_t)R.ny > 8192) return GMF_EINVAL;
     }
+    if (choose_mode(reps, nrep, es, 1) < 0) return GMF_EINVAL;
     return GMF_OK;
 }
 
@@ -167,6 +195,7 @@ struct gmf_ctx {
     bool own_stream = false;
     int npt = kDefaultNpt;
     int grp = 27;                  // storage group size (see gmf_device.hpp)
+    int mode = 0;                  // step-kernel addressing mode (choose_mode)
     uint32_t nblocks = 0;          // lattice grid for the current npt
     int graph_steps = 0;           // 0: direct launches
     int period = 2;                // step pattern period (A/B parity, sampling)
@@ -247,7 +276,7 @@ int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
     a.fields = ctx->d_fields();
     a.partials = ctx->d_partials();
     const bool sample = sampling_step(ctx, t);
-    CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, ctx->grp, ctx->npt, a, ctx->nblocks, ctx->stream));
+    CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, ctx->mode, ctx->npt, a, ctx->nblocks, ctx->stream));
     if (sample) {
         CK(launch_stats_reduce(ctx->d_reps(), ctx->nrep, ctx->d_partials(), ctx->d_acc(), ctx->stream));
         CK(launch_dft(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_plane2rep(), ctx->L.total_planes,
@@ -313,66 +342,103 @@ int run_steps(gmf_ctx* ctx, int64_t n)
     return GMF_OK;
 }
 
-// Time each nodes-per-thread variant on the current state (the step is
-// re-run from the same source buffer, so the state does not advance).
+// Storage layout of every replica for addressing mode m (0: plane-uniform with
+// groups of 27).  Only the host records change; the caller re-uploads them.
+void set_layout(gmf_ctx* ctx, int m)
+{
+    ctx->mode = m;
+    ctx->grp = m == 0 ? 27 : m;
+    for (auto& R : ctx->rdev) {
+        R.grp = (uint32_t)ctx->grp;
+        R.grp_elems = (uint64_t)R.n * R.grp;
+        R.row_stride = R.grp * R.nx;
+    }
+}
+
+// Rest equilibrium in the buffer that the next step reads.
+int init_state(gmf_ctx* ctx)
+{
+    for (int r = 0; r < ctx->nrep; ++r)
+        CK(launch_init(ctx->opt.precision, ctx->pop((int)(ctx->step & 1)), ctx->d_reps() + r, ctx->rdev[r],
+                       ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    return GMF_OK;
+}
+
+// Time every fitting (addressing mode, nodes per thread) pair on the initial
+// state (the same step is re-run from the same source buffer, so the state
+// does not advance), keep the fastest, and restore the initial state in the
+// chosen layout.  Results are cached in the file named by GMF_TUNE_CACHE.
 int autotune(gmf_ctx* ctx)
 {
     const char* cache = getenv("GMF_TUNE_CACHE");
+    const uint64_t es = ctx->opt.precision == GMF_FP32_SHIFTED ? 4 : 8;
     std::string key = "p" + std::to_string(ctx->opt.precision) + "c" + std::to_string(ctx->opt.collision);
     for (auto& r : ctx->reps) key += "_" + std::to_string(r.nx) + "x" + std::to_string(r.ny) + "x" + std::to_string(r.nz);
+    int best_mode = ctx->mode, best_npt = ctx->npt;
+    bool cached = false;
     if (cache) {
         if (FILE* fh = fopen(cache, "r")) {
             char k[4096];
-            int v;
-            while (fscanf(fh, "%4095s %d", k, &v) == 2)
-                if (key == k) {
-                    fclose(fh);
-                    return build_grid(ctx, v);
+            int m, v;
+            while (fscanf(fh, "%4095s %d %d", k, &m, &v) == 3)
+                if (key == k && mode_fits(ctx->reps.data(), ctx->nrep, es, m, v) && (v == 1 || v == 2)) {
+                    best_mode = m;
+                    best_npt = v;
+                    cached = true;
                 }
             fclose(fh);
         }
     }
-    const int cand[2] = {1, 2};
-    hipEvent_t e0, e1;
-    CK(hipEventCreate(&e0));
-    CK(hipEventCreate(&e1));
-    float best_ms = 1e30f;
-    int best = kDefaultNpt;
-    const int reps = 8;
-    for (int c : cand) {
-        int rc = build_grid(ctx, c);
-        if (rc != GMF_OK) return rc;
-        StepArgs a;
-        a.src = ctx->pop((int)(ctx->step & 1));
-        a.dst = ctx->pop((int)(ctx->step & 1) ^ 1);
-        a.reps = ctx->d_reps();
-        a.blk2rep = ctx->d_blk2rep();
-        a.d_step = nullptr;
-        a.step_base = ctx->step;
-        a.fields = nullptr;
-        a.partials = nullptr;
-        CK(launch_step(ctx->opt.precision, ctx->opt.collision, false, ctx->grp, c, a, ctx->nblocks, ctx->stream));
-        CK(hipEventRecord(e0, ctx->stream));
-        for (int i = 0; i < reps; ++i)
-            CK(launch_step(ctx->opt.precision, ctx->opt.collision, false, ctx->grp, c, a, ctx->nblocks, ctx->stream));
-        CK(hipEventRecord(e1, ctx->stream));
-        CK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        CK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = c;
+    if (!cached) {
+        hipEvent_t e0, e1;
+        CK(hipEventCreate(&e0));
+        CK(hipEventCreate(&e1));
+        float best_ms = 1e30f;
+        const int reps = 8;
+        for (int m : {27, 0, 3, 1}) {
+            for (int c : {1, 2}) {
+                if (!mode_fits(ctx->reps.data(), ctx->nrep, es, m, c)) continue;
+                set_layout(ctx, m);
+                int rc = build_grid(ctx, c);
+                if (rc != GMF_OK) return rc;
+                StepArgs a;
+                a.src = ctx->pop((int)(ctx->step & 1));
+                a.dst = ctx->pop((int)(ctx->step & 1) ^ 1);
+                a.reps = ctx->d_reps();
+                a.blk2rep = ctx->d_blk2rep();
+                a.d_step = nullptr;
+                a.step_base = ctx->step;
+                a.fields = nullptr;
+                a.partials = nullptr;
+                CK(launch_step(ctx->opt.precision, ctx->opt.collision, false, m, c, a, ctx->nblocks, ctx->stream));
+                CK(hipEventRecord(e0, ctx->stream));
+                for (int i = 0; i < reps; ++i)
+                    CK(launch_step(ctx->opt.precision, ctx->opt.collision, false, m, c, a, ctx->nblocks, ctx->stream));
+                CK(hipEventRecord(e1, ctx->stream));
+                CK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                CK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_mode = m;
+                    best_npt = c;
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (cache) {
+            if (FILE* fh = fopen(cache, "a")) {
+                fprintf(fh, "%s %d %d\n", key.c_str(), best_mode, best_npt);
+                fclose(fh);
+            }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (cache) {
-        if (FILE* fh = fopen(cache, "a")) {
-            fprintf(fh, "%s %d\n", key.c_str(), best);
-            fclose(fh);
-        }
-    }
-    return build_grid(ctx, best);
+    set_layout(ctx, best_mode);
+    int rc = build_grid(ctx, best_npt);
+    if (rc != GMF_OK) return rc;
+    return init_state(ctx);
 }
 
 uint32_t chunk_planes(const gmf_ctx* ctx, int r)
@@ -440,20 +506,16 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         ctx->own_stream = true;
     }
 
-    // storage group size: the largest of 27, 3, 1 whose byte offsets fit 32
-    // bits in every replica (one value per context: the step kernel is
-    // instantiated for it)
-    {
-        const uint64_t es = opt.precision == GMF_FP32_SHIFTED ? 4 : 8;
-        uint64_t nmax = 0;
-        for (int r = 0; r < nrep; ++r) nmax = std::max<uint64_t>(nmax, (uint64_t)reps[r].nx * reps[r].ny * reps[r].nz);
-        ctx->grp = 1;
-        for (int gsz : {27, 3})
-            if (nmax * (uint64_t)gsz * es < (1ull << 32)) {
-                ctx->grp = gsz;
-                break;
-            }
+    // addressing mode (one per context: the step kernel is instantiated for it)
+    ctx->mode = choose_mode(reps, nrep, opt.precision == GMF_FP32_SHIFTED ? 4 : 8, 1);
+    // GMF_ADDRESSING = plane | 27 | 3 | 1 forces an addressing mode (used by the
+    // tests to run every mode on the same problem; ignored when it does not fit)
+    if (const char* forced = getenv("GMF_ADDRESSING")) {
+        const int m = strcmp(forced, "plane") == 0 ? 0 : atoi(forced);
+        const bool known = strcmp(forced, "plane") == 0 || m == 27 || m == 3 || m == 1;
+        if (known && mode_fits(reps, nrep, opt.precision == GMF_FP32_SHIFTED ? 4 : 8, m, 1)) ctx->mode = m;
     }
+    ctx->grp = ctx->mode == 0 ? 27 : ctx->mode;
     // replica records
     uint64_t pop_off = 0, field_off = 0;
     uint32_t dft_off = 0;
@@ -467,9 +529,6 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         R.nz = (uint32_t)in.nz;
         R.n = R.nx * R.ny * R.nz;
         R.divx = make_fastdiv(R.nx);
-        R.grp = (uint32_t)ctx->grp;
-        R.grp_elems = (uint64_t)R.n * R.grp;
-        R.row_stride = R.grp * R.nx;
         R.divy = make_fastdiv(R.ny);
         R.pop_offset = pop_off;
         R.field_offset = field_off;
@@ -516,16 +575,12 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
     if (gs > 0) gs = ((gs + ctx->period - 1) / ctx->period) * ctx->period;
     ctx->graph_steps = gs;
 
+    set_layout(ctx, ctx->mode);
     rc = build_grid(ctx, kDefaultNpt);
+    if (rc == GMF_OK) rc = init_state(ctx);
     if (rc != GMF_OK) {
         gmf_destroy(ctx);
         return rc;
-    }
-    for (int r = 0; r < nrep; ++r) {
-        if (launch_init(opt.precision, ctx->pop(0), ctx->d_reps() + r, ctx->rdev[r], ctx->stream) != hipSuccess) {
-            gmf_destroy(ctx);
-            return GMF_EDEVICE;
-        }
     }
     if (hipMemsetAsync(ctx->d_acc(), 0, sizeof(double) * kAccStride * nrep, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
@@ -716,12 +771,13 @@ int gmf_get_step(gmf_ctx* ctx, int64_t* t)
     return GMF_OK;
 }
 
-int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int32_t* graphs)
+int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int32_t* graphs, int32_t* addressing)
 {
     if (!ctx) return GMF_ESTATE;
     if (nodes_per_thread) *nodes_per_thread = ctx->npt;
     if (block) *block = kBlock;
     if (graphs) *graphs = ctx->graph_steps;
+    if (addressing) *addressing = ctx->mode;
     return GMF_OK;
 }
 
@@ -752,6 +808,14 @@ int gmf_noise_probe(uint64_t seed, int64_t t, uint32_t node0, int32_t count, int
     if (dn) (void)hipFree(dn);
     (void)hipStreamDestroy(s);
     return rc;
+}
+
+int gmf_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream)
+{
+    if (!src || !dst || bytes == 0 || bytes % 16 != 0 || ((uintptr_t)src % 16) != 0 || ((uintptr_t)dst % 16) != 0)
+        return GMF_EINVAL;
+    if (launch_copy(src, dst, bytes, static_cast<hipStream_t>(hip_stream)) != hipSuccess) return GMF_EDEVICE;
+    return GMF_OK;
 }
 
 void gmf_destroy(gmf_ctx* ctx)

@@ -53,7 +53,7 @@ def test_workspace_bytes_and_validation():
     assert _ws([(0, 16, 16, 1.0, 1.0, 1e-4, 1)]) == 0           # empty box
     assert _ws([(16, 16, 16, 0.0, 1.0, 1e-4, 1)]) == 0          # rho0 <= 0
     assert _ws([(16, 16, 16, 1.0, 1.0, -1e-4, 1)]) == 0         # k_B T < 0
-    assert _ws([(1024, 1024, 1024, 1.0, 1.0, 1e-4, 1)]) == 0    # 32-bit offsets exceeded (FP64)
+    assert _ws([(1001, 1001, 1001, 1.0, 1.0, 1e-4, 1)]) == 0    # no addressing mode fits (FP64)
     assert _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], precision=7) == 0
     assert _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], sample_every=-1) == 0
     assert _ws([(2048, 1024, 1, 1.0, 1.0, 1e-4, 1)], sample_every=10) == 0   # spectra LDS limit

@@ -119,6 +119,29 @@ def test_graph_equals_direct_bitwise():
     assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
 
 
+def test_addressing_modes_bitwise(monkeypatch):
+    """Plane-uniform and per-node addressing with storage groups of 27, 3 and 1
+    give bit-identical trajectories (the layout changes, the arithmetic does
+    not); the autotuner's choice too."""
+    spec = gmf.ReplicaSpec(16, 32, 6, 1.0, 0.6, 1e-4, 21)      # plane of 512 nodes: every mode fits
+    for prec in (gmf.FP64, gmf.FP32_SHIFTED):
+        out = {}
+        for mode in ("", "plane", "27", "3", "1"):
+            monkeypatch.setenv("GMF_ADDRESSING", mode)
+            say(f"addressing mode={mode or 'default'} prec={prec}")
+            with gmf.Context([spec], precision=prec) as ctx:
+                cfg = ctx.config()
+                assert cfg["addressing"] == ("group27" if mode == "" else (mode if mode == "plane" else f"group{mode}"))
+                ctx.step(12)
+                out[mode] = ctx.get_populations()
+        monkeypatch.delenv("GMF_ADDRESSING")
+        with gmf.Context([spec], precision=prec, tune=1) as ctx:
+            ctx.step(12)
+            out["tuned"] = ctx.get_populations()
+        for mode in ("plane", "27", "3", "1", "tuned"):
+            assert np.array_equal(out[""], out[mode]), mode
+
+
 def test_batched_equals_single_bitwise():
     specs = [gmf.ReplicaSpec(16, 16, 16, 1.0, 0.51, 1e-4, 1), gmf.ReplicaSpec(12, 9, 7, 1.0, 2.0, 1e-4, 2),
              gmf.ReplicaSpec(32, 32, 32, 1.0, 0.8, 1e-4, 3)]
