@@ -144,7 +144,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--tune", type=int, default=0)
+    ap.add_argument("--tune", type=int, default=1, help="1: autotune the kernel variant at init (default)")
     ap.add_argument("--skip-extra", action="store_true", help="only the FP32 headline (profiling runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--copy-probe", action="store_true",

@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gmf_math.hpp"
+
 namespace gmf {
 
 constexpr int Q = 27;
@@ -166,9 +168,10 @@ struct Normal<double> {
     {
         const double u1 = ((double)a + 0.5) * 0x1p-32;
         const double u2 = ((double)b + 0.5) * 0x1p-32;
-        const double rad = sqrt(-2.0 * log(u1));
+        // logarithm and sine/cosine specialised to these arguments (gmf_math.hpp)
+        const double rad = sqrt(-2.0 * fp64::log_unit(u1));
         double s, c;
-        sincospi(2.0 * u2, &s, &c);
+        fp64::sincos_2pi(u2, &s, &c);
         r0 = rad * c;
         r1 = rad * s;
     }
