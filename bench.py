@@ -96,6 +96,24 @@ def run_gpu(args, torch, gmf, wl):
             out["batched"] = {"seconds": sec, "nodes": we.nodes, "steps": se, "config": ctx.config(),
                               "workload": we.name}
         torch.cuda.synchronize()
+        # the headline box with the fused sampler on (every 10 steps: variances and shell spectra)
+        with gmf.Context([spec], precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune,
+                         sample_every=10) as ctx:
+            ss = max(20, args.steps // 4)
+            print(f"[bench] fp32 sampled every 10: steps {ss}", file=sys.stderr, flush=True)
+            sec = time_context(ctx, stream, ss, 10, torch)
+            out["sampled"] = {"seconds": sec, "nodes": spec.n, "steps": ss}
+        torch.cuda.synchronize()
+        # 512^3 precision-stress box, both precisions
+        wp = wl.precision_stress("fp32")
+        bp = wp.boxes[0]
+        sp = gmf.ReplicaSpec(*bp.n, rho0=bp.rho0, tau=bp.tau, kbt=bp.kbt, seed=bp.seed)
+        for prec, key, st in ((gmf.FP32_SHIFTED, "fp32_512", 40), (gmf.FP64, "fp64_512", 20)):
+            with gmf.Context([sp], precision=prec, stream=stream, tune=args.tune) as ctx:
+                print(f"[bench] {key}: steps {st}", file=sys.stderr, flush=True)
+                sec = time_context(ctx, stream, st, 4, torch)
+                out[key] = {"seconds": sec, "nodes": sp.n, "steps": st, "config": ctx.config()}
+            torch.cuda.synchronize()
     return out
 
 
@@ -212,6 +230,19 @@ def main():
                                 "ms_per_step": round(r["seconds"] / r["steps"] * 1e3, 5),
                                 "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                                 "steps": r["steps"], "kernel_config": r["config"]}
+    if "sampled" in res:
+        r = res["sampled"]
+        g = r["nodes"] * r["steps"] / r["seconds"] / 1e9
+        line["fp32_sampled_every10"] = {"workload": "d3q27_256cube_fp32_tau0.8 with sampling", "glups": round(g, 4),
+                                        "ms_per_step": round(r["seconds"] / r["steps"] * 1e3, 5),
+                                        "overhead_vs_unsampled": round(glups / g - 1, 4)}
+    for key, bpn, name in (("fp32_512", "fp32", "d3q27_512cube_fp32_tau0.55"), ("fp64_512", "fp64", "d3q27_512cube_fp64_tau0.55")):
+        if key in res:
+            r = res[key]
+            g = r["nodes"] * r["steps"] / r["seconds"] / 1e9
+            gbs = BYTES_PER_NODE[bpn] * g
+            line[key] = {"workload": name, "glups": round(g, 4), "gbs": round(gbs, 1),
+                         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "steps": r["steps"], "kernel_config": r["config"]}
     if not args.no_cpu and int(os.environ.get("RANK", 0)) == 0:
         print("[bench] oracle timing on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline()
