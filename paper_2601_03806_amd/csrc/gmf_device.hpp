@@ -38,6 +38,8 @@ constexpr int kDftPlane = kDftNx * kDftNy;
 constexpr int kShells = 8;
 constexpr int kSpec = 5;
 constexpr int kAccStride = 3 * kObs + kSpec * kShells + 8;  // doubles per replica accumulator
+constexpr int kObsChunks = 1024;     // most workgroups per replica in the observables reduction
+constexpr int kZSplit = 16;          // z chunks of the third DFT stage
 
 __host__ __device__ constexpr int tcx(int p) { return p / 9 - 1; }
 __host__ __device__ constexpr int tcy(int p) { return (p / 3) % 3 - 1; }
@@ -86,12 +88,23 @@ struct RepDev {
     uint32_t grp;             // populations per storage group (27, 3 or 1)
     uint64_t grp_elems;       // elements per storage group (n * grp)
     uint32_t row_stride;      // elements between consecutive rows of a group (grp * nx)
-    uint32_t pad1;
+    uint32_t tw_offset;       // offset (complex values) of the replica's twiddle tables (nx, ny, nz entries)
+    uint32_t obs_chunks;      // workgroups of the observables reduction (<= kObsChunks)
+    uint32_t pad2;
     double rho0;
     double omega;             // 1 / tau
     double one_m_omega;       // 1 - omega
     double amp[8];            // noise amplitudes / sqrt(rho): groups of equal b_k (see host)
 };
+
+// Planes per workgroup of the first shell-spectrum DFT stage: kBlock / nx for
+// nx <= kBlock (one column per thread), else 1 (threads loop over columns).
+__host__ __device__ inline uint32_t dft_planes_per_block(uint32_t nx) { return nx <= (uint32_t)kBlock ? kBlock / nx : 1u; }
+// Dynamic LDS of that stage: y and x twiddles and the y-transformed columns.
+__host__ __device__ inline uint64_t dft_lds_bytes(uint32_t nx, uint32_t ny)
+{
+    return 16ull * (ny + nx + 4ull * dft_planes_per_block(nx) * nx);
+}
 
 // Element offset (inside the replica block) of the start of population p's
 // row at (y, z) = (0, 0): uniform per population, added to the base pointer.

@@ -29,7 +29,7 @@ struct StepArgs {
     const int64_t* d_step;        // device step counter (NULL: step_base is the step)
     int64_t step_base;            // step = step_base + (d_step ? *d_step : 0)
     void* fields;                 // sampled fields (SAMPLE variants)
-    double* partials;             // per-workgroup partial sums (SAMPLE variants)
+    double* partials;             // unused by the step kernel (kept for the sampling kernels)
 };
 
 // lattice kernels
@@ -38,10 +38,16 @@ struct StepArgs {
 hipError_t launch_step(int precision, int collision, bool sample, int grp, int npt, const StepArgs& a,
                        uint32_t nblocks, hipStream_t s);
 hipError_t launch_init(int precision, void* buf, const RepDev* rep_dev, const RepDev& rep, hipStream_t s);
-hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* partials, double* acc,
-                               hipStream_t s);
-hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint16_t* plane2rep,
-                      uint32_t nplanes, const void* fields, double* dft, double* acc, int max_nx, int max_ny,
+// FP64 partials of the observables from the sampled fields: nrep * kObsChunks * kPartialStride doubles
+hipError_t launch_observables(int precision, const RepDev* reps, int32_t nrep, const void* fields, double* partials,
+                              hipStream_t s);
+hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* partials, double* acc, hipStream_t s);
+hipError_t launch_twiddles(const RepDev* reps, int32_t nrep, double2* tw, hipStream_t s);
+// dft: per replica kFields * nz * kDftPlane complex; zbuf: nrep * kFields * kZSplit * 196 complex
+// chunks: workgroups of the first DFT stage, (replica << 16) | chunk index;
+// lds: dynamic LDS bytes = 16 (ny + nx + 4 P nx), maximised over the replicas
+hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint32_t* chunks, uint32_t nchunks,
+                      const void* fields, const double2* tw, double2* dft, double2* zbuf, double* acc, size_t lds,
                       hipStream_t s);
 hipError_t launch_set_step(int64_t* d_step, int64_t value, hipStream_t s);
 hipError_t launch_advance_step(int64_t* d_step, int64_t by, hipStream_t s);

@@ -200,7 +200,9 @@ __device__ __forceinline__ RepDev uniform_rep(const RepDev& in)
     R.grp = sgpr(in.grp);
     R.grp_elems = sgpr64(in.grp_elems);
     R.row_stride = sgpr(in.row_stride);
-    R.pad1 = 0;
+    R.tw_offset = sgpr(in.tw_offset);
+    R.obs_chunks = sgpr(in.obs_chunks);
+    R.pad2 = 0;
     R.rho0 = sgprf(in.rho0);
     R.omega = sgprf(in.omega);
     R.one_m_omega = sgprf(in.one_m_omega);
@@ -220,7 +222,7 @@ constexpr int kPlane = 0;
 
 template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int G>
 __device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, uint32_t n, uint32_t zplane,
-                                            uint64_t t, double* acc)
+                                            uint64_t t)
 {
     const uint32_t nx = R.nx, ny = R.ny, nz = R.nz, N = R.n;
     uint32_t x, y, z;
@@ -354,19 +356,6 @@ __device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, 
         stg_cached(fl + 3ull * N, n, h.jz);
         stg_cached(fl + 4ull * N, n, pdiag);
         stg_cached(fl + 5ull * N, n, poff);
-        double o[kObs];
-        o[0] = (double)drho;
-        o[1] = (double)h.jx; o[2] = (double)h.jy; o[3] = (double)h.jz;
-        o[4] = (double)h.jx + (double)h.jy + (double)h.jz;
-        o[5] = (double)pdiag;
-        o[6] = (double)poff;
-        o[7] = (double)(h.jx * irho); o[8] = (double)(h.jy * irho); o[9] = (double)(h.jz * irho);
-#pragma unroll
-        for (int q = 0; q < kObs; ++q) {
-            acc[2 * q] += o[q];
-            acc[2 * q + 1] += o[q] * o[q];
-        }
-        acc[2 * kObs] += isfinite(o[0]) ? 0.0 : 1.0;
     }
 }
 
@@ -406,17 +395,11 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a)
     const uint32_t base = first + threadIdx.x;
     // plane mode: the whole workgroup lies in z plane first / (nx ny)
     const uint32_t zplane = G == kPlane ? fdiv(fdiv(first, R.divx), R.divy) : 0u;
-    double acc[2 * kObs + 1];
-    if (SAMPLE) {
-#pragma unroll
-        for (int q = 0; q < 2 * kObs + 1; ++q) acc[q] = 0.0;
-    }
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const uint32_t n = base + (uint32_t)(k * kBlock);
-        if (n < R.n) node_update<T, SHIFTED, COLL, SAMPLE, G>(a, R, n, zplane, t, acc);
+        if (n < R.n) node_update<T, SHIFTED, COLL, SAMPLE, G>(a, R, n, zplane, t);
     }
-    if (SAMPLE) block_sum_store<2 * kObs + 1>(acc, a.partials + (size_t)blk * kPartialStride);
 }
 
 template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int G>
@@ -486,19 +469,76 @@ hipError_t launch_init(int precision, void* buf, const RepDev* rep_dev, const Re
 }
 
 // ---------------------------------------------------------------------------
-// Sampling: per-replica reduction of the workgroup partials into the FP64
-// accumulators (spatial mean, mean square and variance of each observable).
+// Sampling: reduction of the workgroup partials into the FP64 accumulators
+// (spatial mean, mean square and variance of each observable).  Two stages
+// with a fixed summation order: kReduceSlices workgroups per replica sum
+// contiguous slices of the partials, then one workgroup per replica adds the
+// slices and updates the accumulators.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void stats_reduce_kernel(const RepDev* reps, const double* partials,
-                                                              double* acc)
+// Observables of the sampled state from the six fields the step kernel wrote
+// (drho, j, sum Pi_aa - 3 rho0 cs2, sum_{a<b} Pi_ab); u = j / (rho0 + drho).
+// Grid (kObsChunks, replicas): each workgroup strides over its replica's nodes
+// and writes FP64 partial sums of every observable, of its square, and the
+// count of non-finite densities.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void observables_kernel(const RepDev* reps, const T* __restrict__ fields,
+                                                             double* partials)
+{
+    const int r = blockIdx.y;
+    const RepDev R = uniform_rep(reps[r]);
+    if (blockIdx.x >= R.obs_chunks) return;
+    constexpr int NV = 2 * kObs + 1;
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    const T* fl = fields + R.field_offset;
+    const uint64_t N = R.n;
+#pragma unroll 4
+    for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < R.n; n += R.obs_chunks * kBlock) {
+        double o[kObs];
+        o[0] = (double)fl[n];
+        o[1] = (double)fl[N + n];
+        o[2] = (double)fl[2 * N + n];
+        o[3] = (double)fl[3 * N + n];
+        o[4] = o[1] + o[2] + o[3];
+        o[5] = (double)fl[4 * N + n];
+        o[6] = (double)fl[5 * N + n];
+        const double irho = 1.0 / (R.rho0 + o[0]);
+        o[7] = o[1] * irho;
+        o[8] = o[2] * irho;
+        o[9] = o[3] * irho;
+#pragma unroll
+        for (int q = 0; q < kObs; ++q) {
+            acc[2 * q] += o[q];
+            acc[2 * q + 1] = fma(o[q], o[q], acc[2 * q + 1]);
+        }
+        acc[2 * kObs] += isfinite(o[0]) ? 0.0 : 1.0;
+    }
+    block_sum_store<NV>(acc, partials + ((size_t)r * kObsChunks + blockIdx.x) * kPartialStride);
+}
+
+hipError_t launch_observables(int precision, const RepDev* reps, int32_t nrep, const void* fields, double* partials,
+                              hipStream_t s)
+{
+    dim3 grid(kObsChunks, nrep);
+    if (precision == kFP64)
+        observables_kernel<double><<<grid, kBlock, 0, s>>>(reps, (const double*)fields, partials);
+    else
+        observables_kernel<float><<<grid, kBlock, 0, s>>>(reps, (const float*)fields, partials);
+    return hipGetLastError();
+}
+
+// The kObsChunks partials of each replica, summed in a fixed order, update
+// the accumulators.
+__global__ __launch_bounds__(kBlock) void stats_accumulate_kernel(const RepDev* reps, const double* partials,
+                                                                  double* acc)
 {
     const RepDev& R = reps[blockIdx.x];
     constexpr int NV = 2 * kObs + 1;
     double v[NV];
-#pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = 0.0;
-    for (uint32_t b = threadIdx.x; b < R.nblocks; b += kBlock) {
-        const double* p = partials + (size_t)(R.block_begin + b) * kPartialStride;
+    for (uint32_t c = threadIdx.x; c < R.obs_chunks; c += kBlock) {
+        const double* p = partials + ((size_t)blockIdx.x * kObsChunks + c) * kPartialStride;
 #pragma unroll
         for (int q = 0; q < NV; ++q) v[q] += p[q];
     }
@@ -521,93 +561,121 @@ __global__ __launch_bounds__(kBlock) void stats_reduce_kernel(const RepDev* reps
 
 hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* partials, double* acc, hipStream_t s)
 {
-    stats_reduce_kernel<<<nrep, kBlock, 0, s>>>(reps, partials, acc);
+    stats_accumulate_kernel<<<nrep, kBlock, 0, s>>>(reps, partials, acc);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Shell spectra.  Stage 1 (one workgroup per (field, z plane)): for each row y
-// the DFT along x at n_x = 0..3, then along y at n_y = -3..3.  Stage 2 (one
-// workgroup per replica): the DFT along z at n_z = -3..3 for the vectors of the
-// shells |n|^2 in {1,2,3,4,5,6,8,9} with n_x >= 0 (a real field has
-// |m(-k)| = |m(k)|, so n_x > 0 counts twice), shell averages into the
-// accumulators.
+// Shell spectra (normalised DFT at the vectors of the shells |n|^2 in
+// {1,2,3,4,5,6,8,9}).  A real field has |m(-k)| = |m(k)|, so only n_x >= 0 is
+// computed and n_x > 0 counts twice.  Twiddles e^{-2 pi i m / L} for the three
+// box lengths of each replica are tabulated once (twiddle_kernel).
+//   Stage 1 (one workgroup per (z plane, field)): one row per thread, DFT along
+//     x at n_x = 0..3 (the twiddle index is the same for every lane), then the
+//     DFT along y at n_y = -3..3 from the rows kept in LDS.
+//   Stage 2 (one workgroup per (replica, field)): DFT along z at n_z = -3..3.
+//   Stage 3 (one workgroup per replica): powers of the five spectra, shell
+//     averages into the accumulators (fixed summation order).
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void dft_plane_kernel(const RepDev* reps, const uint16_t* plane2rep,
-                                                           const T* fields, double2* dft)
+__global__ __launch_bounds__(kBlock) void twiddle_kernel(const RepDev* reps, double2* tw)
 {
-    extern __shared__ double lds[];
-    const uint32_t plane_id = blockIdx.x;
+    const RepDev& R = reps[blockIdx.x];
+    const uint32_t lens[3] = {R.nx, R.ny, R.nz};
+    uint32_t off = R.tw_offset;
+    for (int a = 0; a < 3; ++a) {
+        for (uint32_t m = threadIdx.x; m < lens[a]; m += kBlock) {
+            double sn, cs;
+            sincospi(2.0 * (double)m / (double)lens[a], &sn, &cs);
+            tw[off + m] = make_double2(cs, sn);
+        }
+        off += lens[a];
+    }
+}
+
+hipError_t launch_twiddles(const RepDev* reps, int32_t nrep, double2* tw, hipStream_t s)
+{
+    twiddle_kernel<<<nrep, kBlock, 0, s>>>(reps, tw);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dft_plane_kernel(const RepDev* reps, const uint32_t* chunks,
+                                                           const T* __restrict__ fields,
+                                                           const double2* __restrict__ tw, double2* dft)
+{
+    extern __shared__ double2 lds[];    // y twiddles (ny), x twiddles (nx), Y[plane][x][n_y = 0..3]
+    const uint32_t ck = chunks[blockIdx.x];
     const int fld = blockIdx.y;
-    const int r = plane2rep[plane_id];
-    const RepDev& R = reps[r];
-    uint32_t z = plane_id;
-    for (int q = 0; q < r; ++q) z -= reps[q].nz;
-    const uint32_t nx = R.nx, ny = R.ny;
-    double* twx = lds;                 // cos, sin of 2 pi m / nx
-    double* twy = twx + 2 * nx;        // cos, sin of 2 pi m / ny
-    double* X = twy + 2 * ny;          // ny rows x 4 complex
-    for (uint32_t m = threadIdx.x; m < nx; m += kBlock) {
-        double s, c;
-        sincospi(2.0 * (double)m / (double)nx, &s, &c);
-        twx[2 * m] = c;
-        twx[2 * m + 1] = s;
-    }
-    for (uint32_t m = threadIdx.x; m < ny; m += kBlock) {
-        double s, c;
-        sincospi(2.0 * (double)m / (double)ny, &s, &c);
-        twy[2 * m] = c;
-        twy[2 * m + 1] = s;
+    const int r = (int)(ck >> 16);
+    const RepDev R = uniform_rep(reps[r]);
+    const uint32_t nx = R.nx, ny = R.ny, nz = R.nz;
+    const uint32_t P = dft_planes_per_block(nx);
+    const uint32_t z0 = (ck & 0xffffu) * P;
+    double2* twy_s = lds;
+    double2* twx_s = lds + ny;
+    double2* Ys = lds + ny + nx;
+    const double2* twg = tw + R.tw_offset;
+    for (uint32_t m = threadIdx.x; m < nx + ny; m += kBlock) {
+        if (m < nx) twx_s[m] = twg[m];
+        else twy_s[m - nx] = twg[m];
     }
     __syncthreads();
-    const T* src = fields + R.field_offset + (uint64_t)fld * R.n + (uint64_t)z * nx * ny;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (uint32_t y = wave; y < ny; y += kBlock / 64) {
-        double re[kDftNx], im[kDftNx];
-#pragma unroll
-        for (int q = 0; q < kDftNx; ++q) re[q] = im[q] = 0.0;
-        for (uint32_t x = lane; x < nx; x += 64) {
-            const double v = (double)src[(uint64_t)y * nx + x];
-#pragma unroll
-            for (int q = 0; q < kDftNx; ++q) {
-                uint32_t m = (uint32_t)q * x;
-                while (m >= nx) m -= nx;
-                re[q] += v * twx[2 * m];
-                im[q] -= v * twx[2 * m + 1];
+    const T* src = fields + R.field_offset + (uint64_t)fld * R.n;
+    // y first: one column per thread, coalesced across lanes; n_y = 0..3
+    // (a real column has Y(-n_y) = conj(Y(n_y)))
+    const uint32_t cols = P * nx;                      // columns of this workgroup (all its planes)
+    for (uint32_t c = threadIdx.x; c < (P == 1 ? nx : cols); c += kBlock) {
+        const uint32_t p = c / nx, x = c % nx, z = z0 + p;
+        double y0 = 0.0, y1r = 0.0, y1i = 0.0, y2r = 0.0, y2i = 0.0, y3r = 0.0, y3i = 0.0;
+        if (z < nz) {
+            const T* col = src + (uint64_t)z * nx * ny + x;
+            uint32_t m2 = 0, m3 = 0;
+            for (uint32_t y = 0; y < ny; ++y) {
+                const double v = (double)col[(uint64_t)y * nx];
+                const double2 t1 = twy_s[y], t2 = twy_s[m2], t3 = twy_s[m3];
+                y0 += v;
+                y1r = fma(v, t1.x, y1r);
+                y1i = fma(-v, t1.y, y1i);
+                y2r = fma(v, t2.x, y2r);
+                y2i = fma(-v, t2.y, y2i);
+                y3r = fma(v, t3.x, y3r);
+                y3i = fma(-v, t3.y, y3i);
+                m2 += 2;
+                while (m2 >= ny) m2 -= ny;
+                m3 += 3;
+                while (m3 >= ny) m3 -= ny;
             }
         }
-#pragma unroll
-        for (int q = 0; q < kDftNx; ++q) {
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                re[q] += __shfl_xor(re[q], off, 64);
-                im[q] += __shfl_xor(im[q], off, 64);
-            }
-        }
-        if (lane == 0) {
-#pragma unroll
-            for (int q = 0; q < kDftNx; ++q) {
-                X[(y * kDftNx + q) * 2] = re[q];
-                X[(y * kDftNx + q) * 2 + 1] = im[q];
-            }
-        }
+        double2* Yc = Ys + (uint64_t)c * 4;
+        Yc[0] = make_double2(y0, 0.0);
+        Yc[1] = make_double2(y1r, y1i);
+        Yc[2] = make_double2(y2r, y2i);
+        Yc[3] = make_double2(y3r, y3i);
     }
     __syncthreads();
-    if (threadIdx.x < kDftPlane) {
-        const int q = threadIdx.x / kDftNy;          // n_x
-        const int s = threadIdx.x % kDftNy - 3;      // n_y
+    // then x: item = (plane, n_x, n_y), a sum over the plane's columns
+    for (uint32_t it = threadIdx.x; it < P * kDftPlane; it += kBlock) {
+        const uint32_t p = it / kDftPlane, o = it % kDftPlane;
+        const uint32_t z = z0 + p;
+        if (z >= nz) continue;
+        const uint32_t q = o / kDftNy;
+        const int sy = (int)(o % kDftNy) - 3;
+        const uint32_t ay = (uint32_t)(sy < 0 ? -sy : sy);
+        const double sg = sy < 0 ? -1.0 : 1.0;          // conjugate for negative n_y
+        const double2* Yp = Ys + (uint64_t)p * nx * 4 + ay;
         double re = 0.0, im = 0.0;
-        for (uint32_t y = 0; y < ny; ++y) {
-            int64_t m = ((int64_t)s * (int64_t)y) % (int64_t)ny;
-            if (m < 0) m += ny;
-            const double c = twy[2 * m], sn = twy[2 * m + 1];
-            const double xr = X[(y * kDftNx + q) * 2], xi = X[(y * kDftNx + q) * 2 + 1];
-            // (xr + i xi)(c - i sn)
-            re += xr * c + xi * sn;
-            im += xi * c - xr * sn;
+        uint32_t m = 0;
+        for (uint32_t x = 0; x < nx; ++x) {
+            const double2 yv = Yp[(uint64_t)x * 4];
+            const double yr = yv.x, yi = sg * yv.y;
+            const double2 t = twx_s[m];
+            // (yr + i yi)(c - i s)
+            re += yr * t.x + yi * t.y;
+            im += yi * t.x - yr * t.y;
+            m += q;
+            while (m >= nx) m -= nx;
         }
-        dft[R.dft_offset + ((uint64_t)fld * R.nz + z) * kDftPlane + threadIdx.x] = make_double2(re, im);
+        dft[R.dft_offset + ((uint64_t)fld * nz + z) * kDftPlane + o] = make_double2(re, im);
     }
 }
 
@@ -627,15 +695,51 @@ __device__ __forceinline__ int shell_of(int n2)
 }
 
 __device__ constexpr int kShellCount[kShells] = {6, 12, 8, 6, 24, 24, 12, 30};
+constexpr int kDftVec = kDftNx * kDftNy * 7;   // n_x 0..3, n_y -3..3, n_z -3..3
 
-__global__ __launch_bounds__(kBlock) void dft_shell_kernel(const RepDev* reps, const double2* dft, double* acc)
+// Stage 2: Z[f][v] = sum_z P[f][z][n_x, n_y] e^{-2 pi i n_z z / nz}, in kZSplit
+// partial sums over contiguous z chunks (blockIdx.z)
+__global__ __launch_bounds__(kBlock) void dft_z_kernel(const RepDev* reps, const double2* __restrict__ tw,
+                                                       const double2* __restrict__ dft, double2* zout)
 {
     const RepDev& R = reps[blockIdx.x];
-    constexpr int NVEC = kDftNx * kDftNy * 7;   // n_x 0..3, n_y -3..3, n_z -3..3
-    __shared__ double contrib[NVEC][kSpec];
-    __shared__ int shell[NVEC];
+    const int fld = blockIdx.y;
+    const int zs = blockIdx.z;
     const int v = threadIdx.x;
-    if (v < NVEC) {
+    if (v >= kDftVec) return;
+    const int q = v / (kDftNy * 7);
+    const int sy = (v / 7) % kDftNy - 3;
+    const int u = v % 7 - 3;
+    (void)sy;
+    const int col = q * kDftNy + ((v / 7) % kDftNy);
+    const uint32_t nz = R.nz;
+    const double2* twz = tw + R.tw_offset + R.nx + R.ny;
+    const uint32_t step = (uint32_t)((u % (int)nz + (int)nz) % (int)nz);
+    const uint32_t per = (nz + kZSplit - 1) / kZSplit;
+    const uint32_t z0 = min(nz, zs * per), z1 = min(nz, z0 + per);
+    uint32_t m = (uint32_t)(((uint64_t)step * z0) % nz);
+    double zr = 0.0, zi = 0.0;
+    const double2* P = dft + R.dft_offset + (uint64_t)fld * nz * kDftPlane + col;
+#pragma unroll 8
+    for (uint32_t z = z0; z < z1; ++z) {
+        const double2 p = P[(uint64_t)z * kDftPlane];
+        const double2 t = twz[m];
+        zr += p.x * t.x + p.y * t.y;
+        zi += p.y * t.x - p.x * t.y;
+        m += step;
+        if (m >= nz) m -= nz;
+    }
+    zout[(((size_t)blockIdx.x * kFields + fld) * kZSplit + zs) * kDftVec + v] = make_double2(zr, zi);
+}
+
+// Stage 3: shell averages of the five spectra
+__global__ __launch_bounds__(kBlock) void dft_shell_kernel(const RepDev* reps, const double2* zin, double* acc)
+{
+    const RepDev& R = reps[blockIdx.x];
+    __shared__ double contrib[kDftVec][kSpec];
+    __shared__ int shell[kDftVec];
+    const int v = threadIdx.x;
+    if (v < kDftVec) {
         const int q = v / (kDftNy * 7);
         const int s = (v / 7) % kDftNy - 3;
         const int u = v % 7 - 3;
@@ -645,18 +749,13 @@ __global__ __launch_bounds__(kBlock) void dft_shell_kernel(const RepDev* reps, c
         if (sh >= 0) {
             double zr[kFields], zi[kFields];
 #pragma unroll
-            for (int f = 0; f < kFields; ++f) zr[f] = zi[f] = 0.0;
-            const int col = q * kDftNy + (s + 3);
-            for (uint32_t z = 0; z < R.nz; ++z) {
-                int64_t m = ((int64_t)u * (int64_t)z) % (int64_t)R.nz;
-                if (m < 0) m += R.nz;
-                double sn, c;
-                sincospi(2.0 * (double)m / (double)R.nz, &sn, &c);
-#pragma unroll
-                for (int f = 0; f < kFields; ++f) {
-                    const double2 p = dft[R.dft_offset + ((uint64_t)f * R.nz + z) * kDftPlane + col];
-                    zr[f] += p.x * c + p.y * sn;
-                    zi[f] += p.y * c - p.x * sn;
+            for (int f = 0; f < kFields; ++f) {
+                zr[f] = 0.0;
+                zi[f] = 0.0;
+                for (int zs = 0; zs < kZSplit; ++zs) {
+                    const double2 zz = zin[(((size_t)blockIdx.x * kFields + f) * kZSplit + zs) * kDftVec + v];
+                    zr[f] += zz.x;
+                    zi[f] += zz.y;
                 }
             }
             const double w = (q > 0 ? 2.0 : 1.0) / (double)R.n;
@@ -674,24 +773,27 @@ __global__ __launch_bounds__(kBlock) void dft_shell_kernel(const RepDev* reps, c
     if (threadIdx.x < kSpec * kShells) {
         const int m = threadIdx.x / kShells, sh = threadIdx.x % kShells;
         double s = 0.0;
-        for (int j = 0; j < NVEC; ++j)
+        for (int j = 0; j < kDftVec; ++j)
             if (shell[j] == sh) s += contrib[j][m];
         acc[(size_t)blockIdx.x * kAccStride + kAccSpec + m * kShells + sh] += s / (double)kShellCount[sh];
     }
 }
 
-hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint16_t* plane2rep, uint32_t nplanes,
-                      const void* fields, double* dft, double* acc, int max_nx, int max_ny, hipStream_t s)
+hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint32_t* chunks, uint32_t nchunks,
+                      const void* fields, const double2* tw, double2* dft, double2* zbuf, double* acc, size_t lds,
+                      hipStream_t s)
 {
-    const size_t lds = sizeof(double) * (2 * (size_t)max_nx + 2 * (size_t)max_ny + 2 * kDftNx * (size_t)max_ny);
-    dim3 grid(nplanes, kFields);
+    dim3 grid(nchunks, kFields);
     if (precision == kFP64)
-        dft_plane_kernel<double><<<grid, kBlock, lds, s>>>(reps, plane2rep, (const double*)fields, (double2*)dft);
+        dft_plane_kernel<double><<<grid, kBlock, lds, s>>>(reps, chunks, (const double*)fields, tw, dft);
     else
-        dft_plane_kernel<float><<<grid, kBlock, lds, s>>>(reps, plane2rep, (const float*)fields, (double2*)dft);
+        dft_plane_kernel<float><<<grid, kBlock, lds, s>>>(reps, chunks, (const float*)fields, tw, dft);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dft_shell_kernel<<<nrep, kBlock, 0, s>>>(reps, (const double2*)dft, acc);
+    dft_z_kernel<<<dim3(nrep, kFields, kZSplit), kBlock, 0, s>>>(reps, tw, dft, zbuf);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dft_shell_kernel<<<nrep, kBlock, 0, s>>>(reps, zbuf, acc);
     return hipGetLastError();
 }
 

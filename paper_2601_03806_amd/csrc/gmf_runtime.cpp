@@ -39,7 +39,11 @@ const int kShellCnt[kShells] = {6, 12, 8, 6, 24, 24, 12, 30};
 
 struct Layout {
     size_t pop_bytes = 0, popA = 0, popB = 0, reps = 0, blk2rep = 0, step = 0, acc = 0, tot = 0, mpart = 0;
-    size_t fields = 0, partials = 0, dft = 0, plane2rep = 0, stage = 0, stage_bytes = 0, total = 0;
+    size_t fields = 0, partials = 0, dft = 0, chunks = 0, stage = 0, stage_bytes = 0, total = 0;
+    uint32_t total_chunks = 0;     // workgroups of the first spectrum stage
+    size_t dft_lds = 0;
+    size_t twiddles = 0, zbuf = 0;
+    uint32_t tw_complex = 0;
     uint64_t total_nodes = 0;
     uint32_t max_blocks = 0;     // lattice grid at one node per thread
     uint32_t total_planes = 0;
@@ -98,8 +102,8 @@ int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         if (n >= (1ull << 31) || (uint64_t)R.nx * R.ny * Q * es >= (1ull << 32)) return GMF_EINVAL;
         if (!finite_pos(R.rho0) || !std::isfinite(R.tau) || !(R.tau > 0.5)) return GMF_EINVAL;
         if (!std::isfinite(R.kbt) || R.kbt < 0.0) return GMF_EINVAL;
-        // the spectra keep two twiddle tables and one row of partial sums per y in LDS
-        if (sampling && 2 * (uint64_t)R.nx + 10 * (uint64_t)R.ny > 8192) return GMF_EINVAL;
+        // the first spectrum stage keeps twiddles and y-transformed columns in LDS
+        if (sampling && dft_lds_bytes((uint32_t)R.nx, (uint32_t)R.ny) > 65536) return GMF_EINVAL;
     }
     if (choose_mode(reps, nrep, es, 1) < 0) return GMF_EINVAL;
     return GMF_OK;
@@ -117,7 +121,13 @@ Layout plan(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         L.total_nodes += n;
         L.max_blocks += (uint32_t)((n + kBlock - 1) / kBlock);
         L.total_planes += (uint32_t)reps[r].nz;
+        {
+            const uint32_t P = dft_planes_per_block((uint32_t)reps[r].nx);
+            L.total_chunks += ((uint32_t)reps[r].nz + P - 1) / P;
+            L.dft_lds = std::max<size_t>(L.dft_lds, dft_lds_bytes((uint32_t)reps[r].nx, (uint32_t)reps[r].ny));
+        }
         L.dft_complex += (uint32_t)(kFields * reps[r].nz * kDftPlane);
+        L.tw_complex += (uint32_t)(reps[r].nx + reps[r].ny + reps[r].nz);
         L.max_nx = std::max(L.max_nx, (int)reps[r].nx);
         L.max_ny = std::max(L.max_ny, (int)reps[r].ny);
         // a chunk holds whole z planes: at least one plane, at most kStageCap bytes of FP64 populations
@@ -147,9 +157,11 @@ Layout plan(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
     L.mpart = take(sizeof(double) * 4 * L.max_chunk_blocks);
     if (L.sampling) {
         L.fields = take((size_t)L.total_nodes * kFields * es);
-        L.partials = take(sizeof(double) * kPartialStride * L.max_blocks);
+        L.partials = take(sizeof(double) * kPartialStride * kObsChunks * nrep);
         L.dft = take(sizeof(double) * 2 * L.dft_complex);
-        L.plane2rep = take(sizeof(uint16_t) * L.total_planes);
+        L.chunks = take(sizeof(uint32_t) * L.total_chunks);
+        L.twiddles = take(sizeof(double) * 2 * L.tw_complex);
+        L.zbuf = take(sizeof(double) * 2 * kFields * kZSplit * 196 * nrep);
     }
     L.stage = take(L.stage_bytes);
     L.total = off;
@@ -214,7 +226,9 @@ struct gmf_ctx {
     void* d_fields() { return L.sampling ? ws + L.fields : nullptr; }
     double* d_partials() { return L.sampling ? reinterpret_cast<double*>(ws + L.partials) : nullptr; }
     double* d_dft() { return L.sampling ? reinterpret_cast<double*>(ws + L.dft) : nullptr; }
-    uint16_t* d_plane2rep() { return L.sampling ? reinterpret_cast<uint16_t*>(ws + L.plane2rep) : nullptr; }
+    uint32_t* d_chunks() { return L.sampling ? reinterpret_cast<uint32_t*>(ws + L.chunks) : nullptr; }
+    double2* d_twiddles() { return L.sampling ? reinterpret_cast<double2*>(ws + L.twiddles) : nullptr; }
+    double2* d_zbuf() { return L.sampling ? reinterpret_cast<double2*>(ws + L.zbuf) : nullptr; }
     char* d_stage() { return ws + L.stage; }
 };
 
@@ -278,9 +292,12 @@ int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
     const bool sample = sampling_step(ctx, t);
     CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, ctx->mode, ctx->npt, a, ctx->nblocks, ctx->stream));
     if (sample) {
+        CK(launch_observables(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_fields(), ctx->d_partials(),
+                              ctx->stream));
         CK(launch_stats_reduce(ctx->d_reps(), ctx->nrep, ctx->d_partials(), ctx->d_acc(), ctx->stream));
-        CK(launch_dft(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_plane2rep(), ctx->L.total_planes,
-                      ctx->d_fields(), ctx->d_dft(), ctx->d_acc(), ctx->L.max_nx, ctx->L.max_ny, ctx->stream));
+        CK(launch_dft(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_chunks(), ctx->L.total_chunks,
+                      ctx->d_fields(), ctx->d_twiddles(), reinterpret_cast<double2*>(ctx->d_dft()), ctx->d_zbuf(),
+                      ctx->d_acc(), ctx->L.dft_lds, ctx->stream));
     }
     return GMF_OK;
 }
@@ -518,8 +535,8 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
     ctx->grp = ctx->mode == 0 ? 27 : ctx->mode;
     // replica records
     uint64_t pop_off = 0, field_off = 0;
-    uint32_t dft_off = 0;
-    std::vector<uint16_t> plane2rep;
+    uint32_t dft_off = 0, tw_off = 0;
+    std::vector<uint32_t> chunks;
     for (int r = 0; r < nrep; ++r) {
         const gmf_replica& in = reps[r];
         RepDev R;
@@ -533,6 +550,10 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         R.pop_offset = pop_off;
         R.field_offset = field_off;
         R.dft_offset = dft_off;
+        R.tw_offset = tw_off;
+        // observables reduction: at least 16 nodes per thread, at most kObsChunks workgroups
+        R.obs_chunks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kObsChunks, R.n / (16u * kBlock)));
+        tw_off += R.nx + R.ny + R.nz;
         pop_off += (uint64_t)Q * R.n;
         field_off += (uint64_t)kFields * R.n;
         dft_off += (uint32_t)(kFields * R.nz * kDftPlane);
@@ -550,10 +571,13 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
             R.amp[g] = std::sqrt(in.kbt * (hydro ? relax : 1.0) * kGroupB[g] / kCs2);
         }
         ctx->rdev.push_back(R);
-        if (L.sampling) plane2rep.insert(plane2rep.end(), R.nz, (uint16_t)r);
+        if (L.sampling) {
+            const uint32_t P = dft_planes_per_block(R.nx);
+            for (uint32_t c = 0; c < (R.nz + P - 1) / P; ++c) chunks.push_back(((uint32_t)r << 16) | c);
+        }
     }
     if (L.sampling) {
-        hipError_t e = hipMemcpy(ctx->d_plane2rep(), plane2rep.data(), sizeof(uint16_t) * plane2rep.size(),
+        hipError_t e = hipMemcpy(ctx->d_chunks(), chunks.data(), sizeof(uint32_t) * chunks.size(),
                                  hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             gmf_destroy(ctx);
@@ -578,6 +602,9 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
     set_layout(ctx, ctx->mode);
     rc = build_grid(ctx, kDefaultNpt);
     if (rc == GMF_OK) rc = init_state(ctx);
+    if (rc == GMF_OK && L.sampling) {
+        if (launch_twiddles(ctx->d_reps(), nrep, ctx->d_twiddles(), ctx->stream) != hipSuccess) rc = GMF_EDEVICE;
+    }
     if (rc != GMF_OK) {
         gmf_destroy(ctx);
         return rc;
