@@ -30,7 +30,7 @@ METRIC = "GLUPS & % HBM roofline, FP32-batched vs FP64-plain, at matched varianc
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("gmf_kernels.hip", "gmf_device.hpp"):
+    for f in ("gmf_kernels.hip", "gmf_device.hpp", "gmf_math.hpp"):
         with open(os.path.join(ROOT, "paper_2601_03806_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
