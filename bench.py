@@ -96,6 +96,14 @@ def run_gpu(args, torch, gmf, wl):
             out["batched"] = {"seconds": sec, "nodes": we.nodes, "steps": se, "config": ctx.config(),
                               "workload": we.name}
         torch.cuda.synchronize()
+        # the headline box with the in-place AA pattern (one population buffer: half the memory)
+        with gmf.Context([spec], precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune,
+                         streaming=gmf.STREAM_AA) as ctx:
+            sa = max(20, args.steps // 4)
+            print(f"[bench] fp32 AA streaming: steps {sa}", file=sys.stderr, flush=True)
+            sec = time_context(ctx, stream, sa, args.warmup, torch)
+            out["aa"] = {"seconds": sec, "nodes": spec.n, "steps": sa, "config": ctx.config()}
+        torch.cuda.synchronize()
         # the headline box with the fused sampler on (every 10 steps: variances and shell spectra)
         with gmf.Context([spec], precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune,
                          sample_every=10) as ctx:
@@ -207,7 +215,9 @@ def main():
         "data": "synthetic (equilibrium fluid at rest, rho0=1, Philox noise)",
         "config": {"workload": "d3q27_256cube_fp32_tau0.8", "lattice": [256, 256, 256], "rho0": 1.0,
                    "tau": 0.8, "kbt": 1e-4, "seed": 1, "precision": "fp32_shifted",
-                   "layout": "row-interleaved populations, A/B pull", "kernel_config": r32["config"]},
+                   "layout": "row-interleaved populations, " + ("in-place AA" if r32["config"]["streaming"] == "AA"
+                                                                   else "A/B pull"),
+                   "kernel_config": r32["config"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic("step_fp32_256", r32["nodes"])},
@@ -230,6 +240,14 @@ def main():
                                 "ms_per_step": round(r["seconds"] / r["steps"] * 1e3, 5),
                                 "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                                 "steps": r["steps"], "kernel_config": r["config"]}
+    if "aa" in res:
+        r = res["aa"]
+        g = r["nodes"] * r["steps"] / r["seconds"] / 1e9
+        gbs = BYTES_PER_NODE["fp32"] * g
+        line["fp32_aa_one_buffer"] = {"workload": "d3q27_256cube_fp32_tau0.8, in-place AA streaming",
+                                      "glups": round(g, 4), "gbs": round(gbs, 1),
+                                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "steps": r["steps"],
+                                      "kernel_config": r["config"]}
     if "sampled" in res:
         r = res["sampled"]
         g = r["nodes"] * r["steps"] / r["seconds"] / 1e9

@@ -65,6 +65,14 @@ extern "C" {
 /* gmf_options.collision */
 #define GMF_COLLISION_GMF 0 /* Eq. (10): ghost-mode filtered               */
 #define GMF_COLLISION_BGK 1 /* Eq. (1): BGK-FLBM, noise on k = 4..26 with omega(2-omega) */
+/* gmf_options.streaming: how the populations move between steps.  Both
+ * patterns give bit-identical trajectories; they differ in memory and speed. */
+#define GMF_STREAM_AUTO 0   /* A/B; with tune = 1 the faster of A/B and AA   */
+#define GMF_STREAM_AB 1     /* two population buffers, pull from one into the other */
+#define GMF_STREAM_AA 2     /* one buffer updated in place (even steps pull from the
+                               neighbours and write back where they read, odd steps
+                               read and write the node's own values): half the
+                               population memory */
 
 /* observables accumulated by the sampler (index into gmf_stats_t arrays) */
 #define GMF_NOBS 10
@@ -110,7 +118,8 @@ typedef struct {
     int32_t sample_every; /* > 0: sample f(., t) at every step with t % sample_every == 0; 0: off */
     int32_t graph_steps;  /* steps per captured HIP graph; 0: direct launches; < 0: default (64) */
     int32_t tune;         /* 0: built-in kernel configuration; 1: time the variants at init */
-    int32_t reserved[2];  /* must be 0                                      */
+    int32_t streaming;    /* GMF_STREAM_AUTO, GMF_STREAM_AB or GMF_STREAM_AA */
+    int32_t reserved;     /* must be 0                                      */
 } gmf_options;
 
 typedef struct {
@@ -182,11 +191,13 @@ int gmf_noise_probe(uint64_t seed, int64_t t, uint32_t node0, int32_t count, int
                     uint32_t* words, double* normals);
 
 /* Kernel configuration in use (for reports): nodes per thread, threads per
- * workgroup, steps per captured HIP graph (0: direct launches), and the
+ * workgroup, steps per captured HIP graph (0: direct launches), the
  * addressing mode of the step kernel (0: plane-uniform rows of 27 populations;
- * 27, 3, 1: per-node addressing with storage groups of that many populations).
+ * 27, 3, 1: per-node addressing with storage groups of that many populations)
+ * and the streaming pattern (GMF_STREAM_AB or GMF_STREAM_AA).
  * Any output pointer may be NULL. */
-int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int32_t* graphs, int32_t* addressing);
+int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int32_t* graphs, int32_t* addressing,
+                   int32_t* streaming);
 
 /* Bandwidth reference: enqueue one plain streaming copy of `bytes` (a positive
  * multiple of 16) from device buffer src to device buffer dst (both 16-byte

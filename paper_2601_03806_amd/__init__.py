@@ -26,6 +26,9 @@ FP64 = 0
 FP32_SHIFTED = 1
 COLLISION_GMF = 0
 COLLISION_BGK = 1
+STREAM_AUTO = 0
+STREAM_AB = 1
+STREAM_AA = 2
 
 NOBS = 10
 NSPEC = 5
@@ -50,7 +53,7 @@ class Replica(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("collision", ctypes.c_int32), ("noise_rho", ctypes.c_int32),
                 ("sample_every", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("tune", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("streaming", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -98,8 +101,7 @@ def lib() -> ctypes.CDLL:
         L.gmf_get_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         L.gmf_noise_probe.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32), dp]
-        L.gmf_get_config.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.gmf_get_config.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 5
         L.gmf_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.gmf_copy_probe.restype = ctypes.c_int
         L.gmf_destroy.argtypes = [vp]
@@ -150,10 +152,12 @@ def make_replicas(specs):
     return arr
 
 
-def make_options(precision=FP64, collision=COLLISION_GMF, noise_rho=0, sample_every=0, graph_steps=-1, tune=0):
+def make_options(precision=FP64, collision=COLLISION_GMF, noise_rho=0, sample_every=0, graph_steps=-1, tune=0,
+                 streaming=STREAM_AUTO):
     o = Options()
     o.precision, o.collision, o.noise_rho = precision, collision, noise_rho
     o.sample_every, o.graph_steps, o.tune = sample_every, graph_steps, tune
+    o.streaming = streaming
     return o
 
 
@@ -187,10 +191,10 @@ class Context:
     """
 
     def __init__(self, specs, *, precision=FP64, collision=COLLISION_GMF, noise_rho=0, sample_every=0,
-                 graph_steps=-1, tune=0, workspace="torch", stream=None):
+                 graph_steps=-1, tune=0, streaming=STREAM_AUTO, workspace="torch", stream=None):
         self.specs = list(specs)
         self._reps = make_replicas(self.specs)
-        self._opt = make_options(precision, collision, noise_rho, sample_every, graph_steps, tune)
+        self._opt = make_options(precision, collision, noise_rho, sample_every, graph_steps, tune, streaming)
         self.precision = precision
         self._ws = None
         ws_ptr, ws_bytes = None, 0
@@ -239,11 +243,12 @@ class Context:
         return v.value
 
     def config(self):
-        a, b, c, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().gmf_get_config(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)),
-               "gmf_get_config")
+        a, b, c, d, e = (ctypes.c_int32() for _ in range(5))
+        _check(lib().gmf_get_config(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d),
+                                    ctypes.byref(e)), "gmf_get_config")
         return {"nodes_per_thread": a.value, "block": b.value, "graph_steps": c.value,
-                "addressing": "plane" if d.value == 0 else f"group{d.value}"}
+                "addressing": "plane" if d.value == 0 else f"group{d.value}",
+                "streaming": "AA" if e.value == STREAM_AA else "A/B"}
 
     # data ------------------------------------------------------------------
     def moments(self, r: int = 0):

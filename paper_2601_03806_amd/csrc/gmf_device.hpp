@@ -131,6 +131,32 @@ __host__ __device__ inline uint64_t pop_index(const RepDev& R, int p, uint32_t x
     return pop_base_offset(R, p) + row_offset(R, y, z) + x;
 }
 
+// Streaming patterns of the step kernel.  Tensor order makes the opposite
+// velocity of p the population 26 - p (and its storage slot 26 - slot_of(p)).
+//   kAB       two buffers; read f_p at x - c_p in the source buffer, write f*_p
+//             at x in the other one;
+//   kAAPull   one buffer, steps with even index: read f_p at x - c_p, write
+//             f*_p where f_(26-p) was read (population 26 - p at x + c_p);
+//   kAALocal  one buffer, steps with odd index: read f_p as population 26 - p
+//             at x, write f*_p as population p at x.
+// Each node writes exactly the locations it read, so the in-place update
+// needs no synchronisation between nodes.
+constexpr int kAB = 0, kAAPull = 1, kAALocal = 2;
+__host__ __device__ constexpr int opposite(int p) { return Q - 1 - p; }
+
+// Element offset of the canonical pre-collision value f_p(x, y, z): after a
+// two-buffer step or an even number of AA steps it is population p at x - c_p;
+// after an odd number of AA steps (aa_odd) it is population 26 - p at x.
+__host__ __device__ inline uint64_t canon_index(const RepDev& R, int p, uint32_t x, uint32_t y, uint32_t z,
+                                                int aa_odd)
+{
+    if (aa_odd) return pop_index(R, opposite(p), x, y, z);
+    const uint32_t xs = (x + R.nx - (uint32_t)(tcx(p) + 1) + 1) % R.nx;
+    const uint32_t ys = (y + R.ny - (uint32_t)(tcy(p) + 1) + 1) % R.ny;
+    const uint32_t zs = (z + R.nz - (uint32_t)(tcz(p) + 1) + 1) % R.nz;
+    return pop_index(R, p, xs, ys, zs);
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10: ten rounds of two 32x32->64 multiplies and xors, key bumped by
 // the Weyl constants between rounds (Salmon et al., SC'11).

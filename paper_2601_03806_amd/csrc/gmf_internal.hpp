@@ -33,9 +33,11 @@ struct StepArgs {
 };
 
 // lattice kernels
+// sm: streaming pattern kAB, kAAPull or kAALocal (gmf_device.hpp); the AA
+// patterns need a.src == a.dst.
 // grp: addressing mode shared by every replica of the context: 0 (plane-uniform,
 // storage groups of 27) or the storage group size 27, 3 or 1 (per-node addressing)
-hipError_t launch_step(int precision, int collision, bool sample, int grp, int npt, const StepArgs& a,
+hipError_t launch_step(int precision, int collision, bool sample, int sm, int grp, int npt, const StepArgs& a,
                        uint32_t nblocks, hipStream_t s);
 hipError_t launch_init(int precision, void* buf, const RepDev* rep_dev, const RepDev& rep, hipStream_t s);
 // FP64 partials of the observables from the sampled fields: nrep * kObsChunks * kPartialStride doubles
@@ -52,18 +54,19 @@ hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uin
 hipError_t launch_set_step(int64_t* d_step, int64_t value, hipStream_t s);
 hipError_t launch_advance_step(int64_t* d_step, int64_t by, hipStream_t s);
 
-// host-interface helpers (chunks of z planes of one replica)
+// host-interface helpers (chunks of z planes of one replica); aa_odd: the buffer
+// holds the state after an odd number of AA steps (see canon_index)
 hipError_t launch_gather(int precision, const void* src, const RepDev* rep_dev, const RepDev& rep,
-                         uint32_t z0, uint32_t z1, double* out, hipStream_t s);
+                         uint32_t z0, uint32_t z1, double* out, int aa_odd, hipStream_t s);
 hipError_t launch_scatter(int precision, void* dst, const RepDev* rep_dev, const RepDev& rep,
-                          uint32_t z0, uint32_t z1, const double* in, hipStream_t s);
+                          uint32_t z0, uint32_t z1, const double* in, int aa_odd, hipStream_t s);
 hipError_t launch_moments(int precision, const void* src, const RepDev* rep_dev, const RepDev& rep,
                           uint32_t z0, uint32_t z1, double* rho, double* u, double* partials,
-                          hipStream_t s);
+                          int aa_odd, hipStream_t s);
 hipError_t launch_sum_partials(const double* partials, uint32_t nblocks, double* out4, int accumulate,
                                hipStream_t s);
 hipError_t launch_nodes(int precision, const void* src, const RepDev* rep_dev, const int64_t* nodes,
-                        int32_t count, double* out, hipStream_t s);
+                        int32_t count, double* out, int aa_odd, hipStream_t s);
 hipError_t launch_noise_probe(int precision, uint64_t seed, int64_t t, uint32_t node0, int32_t count,
                               uint32_t* words, double* normals, hipStream_t s);
 

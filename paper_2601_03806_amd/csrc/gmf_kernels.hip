@@ -139,14 +139,18 @@ __device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kNontemporal));
 }
 
+// POLICY: kNontemporal, or 0 (cached) for rows written shifted by one node in x,
+// whose partly covered cache lines the L2 then completes before writing back
+template <int POLICY = kNontemporal>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, kNontemporal);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, POLICY);
 }
+template <int POLICY = kNontemporal>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double v)
 {
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, kNontemporal);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, POLICY);
 }
 
 // resource of the storage group holding population p, and p's row-start offset in it (bytes)
@@ -220,7 +224,7 @@ __device__ __forceinline__ RepDev uniform_rep(const RepDev& in)
 //                 a plane (n_y 27 n_x values) must fit 32-bit offsets.
 constexpr int kPlane = 0;
 
-template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int G>
+template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int G, int SM>
 __device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, uint32_t n, uint32_t zplane,
                                             uint64_t t)
 {
@@ -256,31 +260,41 @@ __device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, 
     const T* src = reinterpret_cast<const T*>(a.src) + R.pop_offset;
     T* dst = reinterpret_cast<T*>(a.dst) + R.pop_offset;
     T f[Q];
+    // kAALocal reads population 26 - p at the node itself
+    constexpr bool kLocal = SM == kAALocal;
     uint32_t self;
     __amdgpu_buffer_rsrc_t wr;   // plane mode: resource of the node's own plane
+    __amdgpu_buffer_rsrc_t rp[3];
+    uint32_t ry[3];
+    uint32_t rows[9];
     if constexpr (G == kPlane) {
         // uniform source planes z - cz, per-node source rows y - cy (bytes inside a plane)
         const uint64_t plane_elems = (uint64_t)ny * R.row_stride;
-        __amdgpu_buffer_rsrc_t rp[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) rp[q] = make_rsrc(src + (uint64_t)zv[q] * plane_elems);
-        uint32_t ry[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) ry[q] = yv[q] * R.row_stride * (uint32_t)sizeof(T);
-#pragma unroll
-        for (int p = 0; p < Q; ++p)
-            f[p] = bload<T>(rp[p % 3], ry[(p / 3) % 3] + xb[p / 9], slot_soff<T, 27>(R, p));
         self = ry[1] + xb[1];
-        wr = make_rsrc(dst + (uint64_t)z * plane_elems);
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            if (kLocal)
+                f[p] = bload<T>(rp[1], self, slot_soff<T, 27>(R, opposite(p)));
+            else
+                f[p] = bload<T>(rp[p % 3], ry[(p / 3) % 3] + xb[p / 9], slot_soff<T, 27>(R, p));
+        }
+        wr = SM == kAB ? make_rsrc(dst + (uint64_t)z * plane_elems) : rp[1];
     } else {
         // byte offsets: source row (y - cy, z - cz) at index 3*cyi + czi
-        uint32_t rows[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) rows[q] = row_offset(R, yv[q / 3], zv[q % 3]) * (uint32_t)sizeof(T);
-#pragma unroll
-        for (int p = 0; p < Q; ++p)
-            f[p] = bload<T>(group_rsrc<T, G>(src, R, p), rows[p % 9] + xb[p / 9], slot_soff<T, G>(R, p));
         self = rows[4] + xb[1];
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            if (kLocal)
+                f[p] = bload<T>(group_rsrc<T, G>(src, R, opposite(p)), self, slot_soff<T, G>(R, opposite(p)));
+            else
+                f[p] = bload<T>(group_rsrc<T, G>(src, R, p), rows[p % 9] + xb[p / 9], slot_soff<T, G>(R, p));
+        }
     }
 
     // noise words do not depend on the populations: issue them while the loads fly
@@ -337,7 +351,27 @@ __device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, 
         for (int p = 0; p < Q; ++p) F[p] += omm * f[p];
     }
 
-    if constexpr (G == kPlane) {
+    if constexpr (SM == kAAPull) {
+        // f*_p goes where f_(26-p) came from: population 26 - p at x + c_p
+        // (rows shifted in x are written through the cache, see bstore)
+        if constexpr (G == kPlane) {
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                const int o = opposite(p);
+                const uint32_t off = ry[(o / 3) % 3] + xb[o / 9], so = slot_soff<T, 27>(R, o);
+                if (o / 9 == 1) bstore(rp[o % 3], off, so, F[p]);
+                else bstore<0>(rp[o % 3], off, so, F[p]);
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                const int o = opposite(p);
+                const uint32_t off = rows[o % 9] + xb[o / 9], so = slot_soff<T, G>(R, o);
+                if (o / 9 == 1) bstore(group_rsrc<T, G>(dst, R, o), off, so, F[p]);
+                else bstore<0>(group_rsrc<T, G>(dst, R, o), off, so, F[p]);
+            }
+        }
+    } else if constexpr (G == kPlane) {
 #pragma unroll
         for (int p = 0; p < Q; ++p) bstore(wr, self, slot_soff<T, 27>(R, p), F[p]);
     } else {
@@ -384,7 +418,7 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* out)
     }
 }
 
-template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int NPT, int G>
+template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int NPT, int G, int SM>
 __global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a)
 {
     const uint32_t blk = blockIdx.x;
@@ -398,49 +432,62 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a)
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const uint32_t n = base + (uint32_t)(k * kBlock);
-        if (n < R.n) node_update<T, SHIFTED, COLL, SAMPLE, G>(a, R, n, zplane, t);
+        if (n < R.n) node_update<T, SHIFTED, COLL, SAMPLE, G, SM>(a, R, n, zplane, t);
     }
 }
 
-template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int G>
+template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int G, int SM>
 static hipError_t launch_step_npt(int npt, const StepArgs& a, uint32_t nblocks, hipStream_t s)
 {
     switch (npt) {
-    case 1: step_kernel<T, SHIFTED, COLL, SAMPLE, 1, G><<<nblocks, kBlock, 0, s>>>(a); break;
-    case 2: step_kernel<T, SHIFTED, COLL, SAMPLE, 2, G><<<nblocks, kBlock, 0, s>>>(a); break;
+    case 1: step_kernel<T, SHIFTED, COLL, SAMPLE, 1, G, SM><<<nblocks, kBlock, 0, s>>>(a); break;
+    case 2: step_kernel<T, SHIFTED, COLL, SAMPLE, 2, G, SM><<<nblocks, kBlock, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <typename T, bool SHIFTED, int COLL, bool SAMPLE>
+template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int SM>
 static hipError_t launch_step_grp(int grp, int npt, const StepArgs& a, uint32_t nb, hipStream_t s)
 {
     switch (grp) {
-    case kPlane: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, kPlane>(npt, a, nb, s);
-    case 27: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, 27>(npt, a, nb, s);
-    case 3: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, 3>(npt, a, nb, s);
-    case 1: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, 1>(npt, a, nb, s);
+    case kPlane: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, kPlane, SM>(npt, a, nb, s);
+    case 27: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, 27, SM>(npt, a, nb, s);
+    case 3: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, 3, SM>(npt, a, nb, s);
+    case 1: return launch_step_npt<T, SHIFTED, COLL, SAMPLE, 1, SM>(npt, a, nb, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, bool SHIFTED, int COLL, bool SAMPLE>
+static hipError_t launch_step_sm(int sm, int grp, int npt, const StepArgs& a, uint32_t nb, hipStream_t s)
+{
+    switch (sm) {
+    case kAB: return launch_step_grp<T, SHIFTED, COLL, SAMPLE, kAB>(grp, npt, a, nb, s);
+    case kAAPull: return launch_step_grp<T, SHIFTED, COLL, SAMPLE, kAAPull>(grp, npt, a, nb, s);
+    case kAALocal: return launch_step_grp<T, SHIFTED, COLL, SAMPLE, kAALocal>(grp, npt, a, nb, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T, bool SHIFTED>
-static hipError_t launch_step_t(int collision, bool sample, int grp, int npt, const StepArgs& a, uint32_t nb,
-                                hipStream_t s)
+static hipError_t launch_step_t(int collision, bool sample, int sm, int grp, int npt, const StepArgs& a,
+                                uint32_t nb, hipStream_t s)
 {
     if (collision == kGMF)
-        return sample ? launch_step_grp<T, SHIFTED, kGMF, true>(grp, npt, a, nb, s)
-                      : launch_step_grp<T, SHIFTED, kGMF, false>(grp, npt, a, nb, s);
-    return sample ? launch_step_grp<T, SHIFTED, kBGK, true>(grp, npt, a, nb, s)
-                  : launch_step_grp<T, SHIFTED, kBGK, false>(grp, npt, a, nb, s);
+        return sample ? launch_step_sm<T, SHIFTED, kGMF, true>(sm, grp, npt, a, nb, s)
+                      : launch_step_sm<T, SHIFTED, kGMF, false>(sm, grp, npt, a, nb, s);
+    return sample ? launch_step_sm<T, SHIFTED, kBGK, true>(sm, grp, npt, a, nb, s)
+                  : launch_step_sm<T, SHIFTED, kBGK, false>(sm, grp, npt, a, nb, s);
 }
 
-hipError_t launch_step(int precision, int collision, bool sample, int grp, int npt, const StepArgs& a,
+hipError_t launch_step(int precision, int collision, bool sample, int sm, int grp, int npt, const StepArgs& a,
                        uint32_t nblocks, hipStream_t s)
 {
-    if (precision == kFP64) return launch_step_t<double, false>(collision, sample, grp, npt, a, nblocks, s);
-    return launch_step_t<float, true>(collision, sample, grp, npt, a, nblocks, s);
+    // the AA patterns update one buffer in place
+    if (sm != kAB && a.src != a.dst) return hipErrorInvalidValue;
+    if (precision == kFP64) return launch_step_t<double, false>(collision, sample, sm, grp, npt, a, nblocks, s);
+    return launch_step_t<float, true>(collision, sample, sm, grp, npt, a, nblocks, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -851,10 +898,10 @@ static CanonMap make_canon_map()
     return m;
 }
 
-// canonical f(x) = stored_p(x - c_p) (+ w_p rho0 when shifted), planes z0 <= z < z1
+// canonical f(x) (+ w_p rho0 when shifted, see canon_index), planes z0 <= z < z1
 template <typename T, bool SHIFTED>
 __global__ __launch_bounds__(kBlock) void gather_kernel(const T* src, const RepDev* rep, uint32_t z0, uint32_t z1,
-                                                        double* out, CanonMap cm)
+                                                        double* out, CanonMap cm, int aa_odd)
 {
     const RepDev& R = *rep;
     const uint64_t plane = (uint64_t)R.nx * R.ny;
@@ -867,10 +914,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(const T* src, const RepD
     const T* s = src + R.pop_offset;
     for (int i = 0; i < Q; ++i) {
         const int p = cm.tensor_of[i];
-        const uint32_t xs = (x + R.nx - tcx(p)) % R.nx;
-        const uint32_t ys = (y + R.ny - tcy(p)) % R.ny;
-        const uint32_t zs = (z + R.nz - tcz(p)) % R.nz;
-        double v = (double)s[pop_index(R, p, xs, ys, zs)];
+        double v = (double)s[canon_index(R, p, x, y, z, aa_odd)];
         if (SHIFTED) v += tweight(p) * R.rho0;
         out[(uint64_t)i * cnt + idx] = v;
     }
@@ -878,7 +922,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(const T* src, const RepD
 
 template <typename T, bool SHIFTED>
 __global__ __launch_bounds__(kBlock) void scatter_kernel(T* dst, const RepDev* rep, uint32_t z0, uint32_t z1,
-                                                         const double* in, CanonMap cm)
+                                                         const double* in, CanonMap cm, int aa_odd)
 {
     const RepDev& R = *rep;
     const uint64_t plane = (uint64_t)R.nx * R.ny;
@@ -891,19 +935,17 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(T* dst, const RepDev* r
     T* d = dst + R.pop_offset;
     for (int i = 0; i < Q; ++i) {
         const int p = cm.tensor_of[i];
-        const uint32_t xs = (x + R.nx - tcx(p)) % R.nx;
-        const uint32_t ys = (y + R.ny - tcy(p)) % R.ny;
-        const uint32_t zs = (z + R.nz - tcz(p)) % R.nz;
         double v = in[(uint64_t)i * cnt + idx];
         if (SHIFTED) v -= tweight(p) * R.rho0;
-        d[pop_index(R, p, xs, ys, zs)] = (T)v;
+        d[canon_index(R, p, x, y, z, aa_odd)] = (T)v;
     }
 }
 
 // density and velocity of the canonical state plus FP64 workgroup sums of rho, j
 template <typename T, bool SHIFTED>
 __global__ __launch_bounds__(kBlock) void moments_kernel(const T* src, const RepDev* rep, uint32_t z0, uint32_t z1,
-                                                         double* rho_out, double* u_out, double* partials)
+                                                         double* rho_out, double* u_out, double* partials,
+                                                         int aa_odd)
 {
     const RepDev& R = *rep;
     const uint64_t plane = (uint64_t)R.nx * R.ny;
@@ -917,10 +959,7 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(const T* src, const Rep
         const T* s = src + R.pop_offset;
         double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
         for (int p = 0; p < Q; ++p) {
-            const uint32_t xs = (x + R.nx - tcx(p)) % R.nx;
-            const uint32_t ys = (y + R.ny - tcy(p)) % R.ny;
-            const uint32_t zs = (z + R.nz - tcz(p)) % R.nz;
-            double fv = (double)s[pop_index(R, p, xs, ys, zs)];
+            double fv = (double)s[canon_index(R, p, x, y, z, aa_odd)];
             if (SHIFTED) fv += tweight(p) * R.rho0;
             rho += fv;
             jx += fv * tcx(p);
@@ -952,7 +991,7 @@ __global__ __launch_bounds__(kBlock) void sum_partials_kernel(const double* part
 
 template <typename T, bool SHIFTED>
 __global__ __launch_bounds__(kBlock) void nodes_kernel(const T* src, const RepDev* rep, const int64_t* nodes,
-                                                       int32_t count, double* out, CanonMap cm)
+                                                       int32_t count, double* out, CanonMap cm, int aa_odd)
 {
     const RepDev& R = *rep;
     const int j = blockIdx.x * kBlock + threadIdx.x;
@@ -964,10 +1003,7 @@ __global__ __launch_bounds__(kBlock) void nodes_kernel(const T* src, const RepDe
     const T* s = src + R.pop_offset;
     for (int i = 0; i < Q; ++i) {
         const int p = cm.tensor_of[i];
-        const uint32_t xs = (x + R.nx - tcx(p)) % R.nx;
-        const uint32_t ys = (y + R.ny - tcy(p)) % R.ny;
-        const uint32_t zs = (z + R.nz - tcz(p)) % R.nz;
-        double v = (double)s[pop_index(R, p, xs, ys, zs)];
+        double v = (double)s[canon_index(R, p, x, y, z, aa_odd)];
         if (SHIFTED) v += tweight(p) * R.rho0;
         out[(size_t)j * Q + i] = v;
     }
@@ -976,37 +1012,37 @@ __global__ __launch_bounds__(kBlock) void nodes_kernel(const T* src, const RepDe
 static inline uint32_t grid_for(uint64_t cnt) { return (uint32_t)((cnt + kBlock - 1) / kBlock); }
 
 hipError_t launch_gather(int precision, const void* src, const RepDev* rep_dev, const RepDev& rep, uint32_t z0,
-                         uint32_t z1, double* out, hipStream_t s)
+                         uint32_t z1, double* out, int aa_odd, hipStream_t s)
 {
     const uint32_t g = grid_for((uint64_t)rep.nx * rep.ny * (z1 - z0));
     static const CanonMap cm = make_canon_map();
     if (precision == kFP64)
-        gather_kernel<double, false><<<g, kBlock, 0, s>>>((const double*)src, rep_dev, z0, z1, out, cm);
+        gather_kernel<double, false><<<g, kBlock, 0, s>>>((const double*)src, rep_dev, z0, z1, out, cm, aa_odd);
     else
-        gather_kernel<float, true><<<g, kBlock, 0, s>>>((const float*)src, rep_dev, z0, z1, out, cm);
+        gather_kernel<float, true><<<g, kBlock, 0, s>>>((const float*)src, rep_dev, z0, z1, out, cm, aa_odd);
     return hipGetLastError();
 }
 
 hipError_t launch_scatter(int precision, void* dst, const RepDev* rep_dev, const RepDev& rep, uint32_t z0,
-                          uint32_t z1, const double* in, hipStream_t s)
+                          uint32_t z1, const double* in, int aa_odd, hipStream_t s)
 {
     const uint32_t g = grid_for((uint64_t)rep.nx * rep.ny * (z1 - z0));
     static const CanonMap cm = make_canon_map();
     if (precision == kFP64)
-        scatter_kernel<double, false><<<g, kBlock, 0, s>>>((double*)dst, rep_dev, z0, z1, in, cm);
+        scatter_kernel<double, false><<<g, kBlock, 0, s>>>((double*)dst, rep_dev, z0, z1, in, cm, aa_odd);
     else
-        scatter_kernel<float, true><<<g, kBlock, 0, s>>>((float*)dst, rep_dev, z0, z1, in, cm);
+        scatter_kernel<float, true><<<g, kBlock, 0, s>>>((float*)dst, rep_dev, z0, z1, in, cm, aa_odd);
     return hipGetLastError();
 }
 
 hipError_t launch_moments(int precision, const void* src, const RepDev* rep_dev, const RepDev& rep, uint32_t z0,
-                          uint32_t z1, double* rho, double* u, double* partials, hipStream_t s)
+                          uint32_t z1, double* rho, double* u, double* partials, int aa_odd, hipStream_t s)
 {
     const uint32_t g = grid_for((uint64_t)rep.nx * rep.ny * (z1 - z0));
     if (precision == kFP64)
-        moments_kernel<double, false><<<g, kBlock, 0, s>>>((const double*)src, rep_dev, z0, z1, rho, u, partials);
+        moments_kernel<double, false><<<g, kBlock, 0, s>>>((const double*)src, rep_dev, z0, z1, rho, u, partials, aa_odd);
     else
-        moments_kernel<float, true><<<g, kBlock, 0, s>>>((const float*)src, rep_dev, z0, z1, rho, u, partials);
+        moments_kernel<float, true><<<g, kBlock, 0, s>>>((const float*)src, rep_dev, z0, z1, rho, u, partials, aa_odd);
     return hipGetLastError();
 }
 
@@ -1017,14 +1053,14 @@ hipError_t launch_sum_partials(const double* partials, uint32_t nblocks, double*
 }
 
 hipError_t launch_nodes(int precision, const void* src, const RepDev* rep_dev, const int64_t* nodes, int32_t count,
-                        double* out, hipStream_t s)
+                        double* out, int aa_odd, hipStream_t s)
 {
     static const CanonMap cm = make_canon_map();
     const uint32_t g = grid_for((uint64_t)count);
     if (precision == kFP64)
-        nodes_kernel<double, false><<<g, kBlock, 0, s>>>((const double*)src, rep_dev, nodes, count, out, cm);
+        nodes_kernel<double, false><<<g, kBlock, 0, s>>>((const double*)src, rep_dev, nodes, count, out, cm, aa_odd);
     else
-        nodes_kernel<float, true><<<g, kBlock, 0, s>>>((const float*)src, rep_dev, nodes, count, out, cm);
+        nodes_kernel<float, true><<<g, kBlock, 0, s>>>((const float*)src, rep_dev, nodes, count, out, cm, aa_odd);
     return hipGetLastError();
 }
 

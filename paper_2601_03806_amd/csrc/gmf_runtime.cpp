@@ -1,9 +1,10 @@
 // gmf_runtime.cpp -- host runtime and C ABI of the GMF-FLBM library (see gmf.h).
 //
-// A context owns: the replica table, two population buffers (A/B pull
-// scheme: the step with index t reads buffer t%2 and writes the other), the
-// sampling buffers and FP64 accumulators, a staging area for host transfers,
-// the device step counter and the captured step-loop graphs.
+// A context owns: the replica table, the population buffers (two for the A/B
+// pull scheme, where the step with index t reads buffer t%2 and writes the
+// other; one for the in-place AA scheme), the sampling buffers and FP64
+// accumulators, a staging area for host transfers, the device step counter
+// and the captured step-loop graphs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,7 +39,8 @@ const int kShellN2[kShells] = {1, 2, 3, 4, 5, 6, 8, 9};
 const int kShellCnt[kShells] = {6, 12, 8, 6, 24, 24, 12, 30};
 
 struct Layout {
-    size_t pop_bytes = 0, popA = 0, popB = 0, reps = 0, blk2rep = 0, step = 0, acc = 0, tot = 0, mpart = 0;
+    size_t pop_bytes = 0, popA = 0, popB = 0;   // popB == popA: one buffer (AA only)
+    size_t reps = 0, blk2rep = 0, step = 0, acc = 0, tot = 0, mpart = 0;
     size_t fields = 0, partials = 0, dft = 0, chunks = 0, stage = 0, stage_bytes = 0, total = 0;
     uint32_t total_chunks = 0;     // workgroups of the first spectrum stage
     size_t dft_lds = 0;
@@ -90,7 +92,8 @@ int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         if (opt->collision != GMF_COLLISION_GMF && opt->collision != GMF_COLLISION_BGK) return GMF_EINVAL;
         if (opt->noise_rho != 0 && opt->noise_rho != 1) return GMF_EINVAL;
         if (opt->sample_every < 0 || opt->tune < 0 || opt->tune > 1) return GMF_EINVAL;
-        if (opt->reserved[0] != 0 || opt->reserved[1] != 0) return GMF_EINVAL;
+        if (opt->streaming < GMF_STREAM_AUTO || opt->streaming > GMF_STREAM_AA || opt->reserved != 0)
+            return GMF_EINVAL;
     }
     const size_t es = (opt && opt->precision == GMF_FP32_SHIFTED) ? 4 : 8;
     const bool sampling = opt && opt->sample_every > 0;
@@ -148,7 +151,7 @@ Layout plan(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
     };
     L.pop_bytes = (size_t)L.total_nodes * Q * es;
     L.popA = take(L.pop_bytes);
-    L.popB = take(L.pop_bytes);
+    L.popB = (opt && opt->streaming == GMF_STREAM_AA) ? L.popA : take(L.pop_bytes);
     L.reps = take(sizeof(RepDev) * nrep);
     L.blk2rep = take(sizeof(uint16_t) * L.max_blocks);
     L.step = take(sizeof(int64_t));
@@ -208,6 +211,7 @@ struct gmf_ctx {
     int npt = kDefaultNpt;
     int grp = 27;                  // storage group size (see gmf_device.hpp)
     int mode = 0;                  // step-kernel addressing mode (choose_mode)
+    bool aa = false;               // in-place AA streaming (else A/B)
     uint32_t nblocks = 0;          // lattice grid for the current npt
     int graph_steps = 0;           // 0: direct launches
     int period = 2;                // step pattern period (A/B parity, sampling)
@@ -217,6 +221,9 @@ struct gmf_ctx {
     bool poisoned = false;
 
     void* pop(int which) { return ws + (which ? L.popB : L.popA); }
+    // buffer holding the state f(., step) and how it is stored there (canon_index)
+    void* cur_pop() { return aa ? pop(0) : pop((int)(step & 1)); }
+    int aa_odd() const { return aa && (step & 1) ? 1 : 0; }
     RepDev* d_reps() { return reinterpret_cast<RepDev*>(ws + L.reps); }
     uint16_t* d_blk2rep() { return nrep > 1 ? reinterpret_cast<uint16_t*>(ws + L.blk2rep) : nullptr; }
     int64_t* d_step() { return reinterpret_cast<int64_t*>(ws + L.step); }
@@ -277,12 +284,14 @@ bool sampling_step(const gmf_ctx* ctx, int64_t t)
 
 // Enqueue the step with index t.  In a graph (in_graph) the kernels read the
 // step from the device counter plus offset j.
+int step_pattern(const gmf_ctx* ctx, int64_t t) { return ctx->aa ? ((t & 1) ? kAALocal : kAAPull) : kAB; }
+
 int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
 {
-    const int par = (int)(t & 1);
+    const int par = ctx->aa ? 0 : (int)(t & 1);
     StepArgs a;
     a.src = ctx->pop(par);
-    a.dst = ctx->pop(par ^ 1);
+    a.dst = ctx->pop(ctx->aa ? 0 : par ^ 1);
     a.reps = ctx->d_reps();
     a.blk2rep = ctx->d_blk2rep();
     a.d_step = in_graph ? ctx->d_step() : nullptr;
@@ -290,7 +299,8 @@ int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
     a.fields = ctx->d_fields();
     a.partials = ctx->d_partials();
     const bool sample = sampling_step(ctx, t);
-    CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, ctx->mode, ctx->npt, a, ctx->nblocks, ctx->stream));
+    CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, step_pattern(ctx, t), ctx->mode, ctx->npt, a,
+                   ctx->nblocks, ctx->stream));
     if (sample) {
         CK(launch_observables(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_fields(), ctx->d_partials(),
                               ctx->stream));
@@ -376,32 +386,42 @@ void set_layout(gmf_ctx* ctx, int m)
 int init_state(gmf_ctx* ctx)
 {
     for (int r = 0; r < ctx->nrep; ++r)
-        CK(launch_init(ctx->opt.precision, ctx->pop((int)(ctx->step & 1)), ctx->d_reps() + r, ctx->rdev[r],
+        CK(launch_init(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, ctx->rdev[r],
                        ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
     return GMF_OK;
 }
 
-// Time every fitting (addressing mode, nodes per thread) pair on the initial
-// state (the same step is re-run from the same source buffer, so the state
-// does not advance), keep the fastest, and restore the initial state in the
-// chosen layout.  Results are cached in the file named by GMF_TUNE_CACHE.
+// Time every fitting (streaming pattern, addressing mode, nodes per thread)
+// triple on the initial state, keep the fastest, and restore the initial state
+// in the chosen layout.  A/B re-runs the same step from the same source buffer;
+// AA alternates its two step kinds in place (the state then changes, which
+// does not matter for the timing and is undone by the re-initialisation).
+// AA is a candidate only when the options leave the pattern open; A/B only
+// when the workspace has its second buffer.  Results are cached in the file
+// named by GMF_TUNE_CACHE.
 int autotune(gmf_ctx* ctx)
 {
     const char* cache = getenv("GMF_TUNE_CACHE");
     const uint64_t es = ctx->opt.precision == GMF_FP32_SHIFTED ? 4 : 8;
-    std::string key = "p" + std::to_string(ctx->opt.precision) + "c" + std::to_string(ctx->opt.collision);
+    std::vector<int> patterns;
+    if (ctx->opt.streaming != GMF_STREAM_AA) patterns.push_back(GMF_STREAM_AB);
+    if (ctx->opt.streaming != GMF_STREAM_AB) patterns.push_back(GMF_STREAM_AA);
+    std::string key = "v2p" + std::to_string(ctx->opt.precision) + "c" + std::to_string(ctx->opt.collision) + "s" +
+                      std::to_string(ctx->opt.streaming);
     for (auto& r : ctx->reps) key += "_" + std::to_string(r.nx) + "x" + std::to_string(r.ny) + "x" + std::to_string(r.nz);
-    int best_mode = ctx->mode, best_npt = ctx->npt;
+    int best_mode = ctx->mode, best_npt = ctx->npt, best_pat = ctx->aa ? GMF_STREAM_AA : GMF_STREAM_AB;
     bool cached = false;
     if (cache) {
         if (FILE* fh = fopen(cache, "r")) {
             char k[4096];
-            int m, v;
-            while (fscanf(fh, "%4095s %d %d", k, &m, &v) == 3)
-                if (key == k && mode_fits(ctx->reps.data(), ctx->nrep, es, m, v) && (v == 1 || v == 2)) {
+            int m, v, sp;
+            while (fscanf(fh, "%4095s %d %d %d", k, &m, &v, &sp) == 4)
+                if (key == k && mode_fits(ctx->reps.data(), ctx->nrep, es, m, v) && (v == 1 || v == 2) &&
+                    std::find(patterns.begin(), patterns.end(), sp) != patterns.end()) {
                     best_mode = m;
                     best_npt = v;
+                    best_pat = sp;
                     cached = true;
                 }
             fclose(fh);
@@ -412,34 +432,43 @@ int autotune(gmf_ctx* ctx)
         CK(hipEventCreate(&e0));
         CK(hipEventCreate(&e1));
         float best_ms = 1e30f;
-        const int reps = 8;
-        for (int m : {27, 0, 3, 1}) {
-            for (int c : {1, 2}) {
-                if (!mode_fits(ctx->reps.data(), ctx->nrep, es, m, c)) continue;
-                set_layout(ctx, m);
-                int rc = build_grid(ctx, c);
-                if (rc != GMF_OK) return rc;
-                StepArgs a;
-                a.src = ctx->pop((int)(ctx->step & 1));
-                a.dst = ctx->pop((int)(ctx->step & 1) ^ 1);
-                a.reps = ctx->d_reps();
-                a.blk2rep = ctx->d_blk2rep();
-                a.d_step = nullptr;
-                a.step_base = ctx->step;
-                a.fields = nullptr;
-                a.partials = nullptr;
-                CK(launch_step(ctx->opt.precision, ctx->opt.collision, false, m, c, a, ctx->nblocks, ctx->stream));
-                CK(hipEventRecord(e0, ctx->stream));
-                for (int i = 0; i < reps; ++i)
-                    CK(launch_step(ctx->opt.precision, ctx->opt.collision, false, m, c, a, ctx->nblocks, ctx->stream));
-                CK(hipEventRecord(e1, ctx->stream));
-                CK(hipEventSynchronize(e1));
-                float ms = 0.f;
-                CK(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best_mode = m;
-                    best_npt = c;
+        const int reps = 8;   // even: AA runs whole pull/local pairs
+        for (int pat : patterns) {
+            for (int m : {27, 0, 3, 1}) {
+                for (int c : {1, 2}) {
+                    if (!mode_fits(ctx->reps.data(), ctx->nrep, es, m, c)) continue;
+                    set_layout(ctx, m);
+                    int rc = build_grid(ctx, c);
+                    if (rc != GMF_OK) return rc;
+                    const bool aa = pat == GMF_STREAM_AA;
+                    StepArgs a;
+                    a.src = ctx->pop(0);
+                    a.dst = ctx->pop(aa ? 0 : 1);
+                    a.reps = ctx->d_reps();
+                    a.blk2rep = ctx->d_blk2rep();
+                    a.d_step = nullptr;
+                    a.step_base = ctx->step;
+                    a.fields = nullptr;
+                    a.partials = nullptr;
+                    auto launch = [&](int i) {
+                        const int sm = aa ? ((i & 1) ? kAALocal : kAAPull) : kAB;
+                        return launch_step(ctx->opt.precision, ctx->opt.collision, false, sm, m, c, a, ctx->nblocks,
+                                           ctx->stream);
+                    };
+                    CK(launch(0));
+                    CK(launch(1));
+                    CK(hipEventRecord(e0, ctx->stream));
+                    for (int i = 0; i < reps; ++i) CK(launch(i));
+                    CK(hipEventRecord(e1, ctx->stream));
+                    CK(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    CK(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best_mode = m;
+                        best_npt = c;
+                        best_pat = pat;
+                    }
                 }
             }
         }
@@ -447,11 +476,12 @@ int autotune(gmf_ctx* ctx)
         (void)hipEventDestroy(e1);
         if (cache) {
             if (FILE* fh = fopen(cache, "a")) {
-                fprintf(fh, "%s %d %d\n", key.c_str(), best_mode, best_npt);
+                fprintf(fh, "%s %d %d %d\n", key.c_str(), best_mode, best_npt, best_pat);
                 fclose(fh);
             }
         }
     }
+    ctx->aa = best_pat == GMF_STREAM_AA;
     set_layout(ctx, best_mode);
     int rc = build_grid(ctx, best_npt);
     if (rc != GMF_OK) return rc;
@@ -533,6 +563,7 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         if (known && mode_fits(reps, nrep, opt.precision == GMF_FP32_SHIFTED ? 4 : 8, m, 1)) ctx->mode = m;
     }
     ctx->grp = ctx->mode == 0 ? 27 : ctx->mode;
+    ctx->aa = opt.streaming == GMF_STREAM_AA;
     // replica records
     uint64_t pop_off = 0, field_off = 0;
     uint32_t dft_off = 0, tw_off = 0;
@@ -648,8 +679,8 @@ int gmf_moments(gmf_ctx* ctx, int32_t r, double* rho, double* u)
         const uint32_t z1 = std::min(R.nz, z0 + cp);
         const uint64_t cnt = plane * (z1 - z0);
         double* su = srho + cnt;
-        CK(launch_moments(ctx->opt.precision, ctx->pop((int)(ctx->step & 1)), ctx->d_reps() + r, R, z0, z1, srho,
-                          su, ctx->d_mpart(), ctx->stream));
+        CK(launch_moments(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, srho, su,
+                          ctx->d_mpart(), ctx->aa_odd(), ctx->stream));
         CK(hipStreamSynchronize(ctx->stream));
         if (rho) CK(hipMemcpy(rho + plane * z0, srho, sizeof(double) * cnt, hipMemcpyDeviceToHost));
         if (u)
@@ -674,8 +705,8 @@ int gmf_stats(gmf_ctx* ctx, int32_t r, gmf_stats_t* out)
         const uint32_t z1 = std::min(R.nz, z0 + cp);
         const uint64_t cnt = plane * (z1 - z0);
         const uint32_t nb = (uint32_t)((cnt + kBlock - 1) / kBlock);
-        CK(launch_moments(ctx->opt.precision, ctx->pop((int)(ctx->step & 1)), ctx->d_reps() + r, R, z0, z1, nullptr,
-                          nullptr, ctx->d_mpart(), ctx->stream));
+        CK(launch_moments(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, nullptr, nullptr,
+                          ctx->d_mpart(), ctx->aa_odd(), ctx->stream));
         CK(launch_sum_partials(ctx->d_mpart(), nb, ctx->d_tot(), first ? 0 : 1, ctx->stream));
         first = false;
     }
@@ -729,7 +760,7 @@ int gmf_get_populations(gmf_ctx* ctx, int32_t r, double* f)
     for (uint32_t z0 = 0; z0 < R.nz; z0 += cp) {
         const uint32_t z1 = std::min(R.nz, z0 + cp);
         const uint64_t cnt = plane * (z1 - z0);
-        CK(launch_gather(ctx->opt.precision, ctx->pop((int)(ctx->step & 1)), ctx->d_reps() + r, R, z0, z1, st,
+        CK(launch_gather(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, st, ctx->aa_odd(),
                          ctx->stream));
         CK(hipStreamSynchronize(ctx->stream));
         for (int i = 0; i < Q; ++i)
@@ -756,7 +787,7 @@ int gmf_set_populations(gmf_ctx* ctx, int32_t r, const double* f)
         for (int i = 0; i < Q; ++i)
             CK(hipMemcpy(st + (uint64_t)i * cnt, f + (uint64_t)i * R.n + plane * z0, sizeof(double) * cnt,
                          hipMemcpyHostToDevice));
-        CK(launch_scatter(ctx->opt.precision, ctx->pop((int)(ctx->step & 1)), ctx->d_reps() + r, R, z0, z1, st,
+        CK(launch_scatter(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, st, ctx->aa_odd(),
                           ctx->stream));
         CK(hipStreamSynchronize(ctx->stream));
     }
@@ -782,7 +813,7 @@ int gmf_get_nodes(gmf_ctx* ctx, int32_t r, const int64_t* nodes, int32_t count, 
         double* dout = reinterpret_cast<double*>(st + align_up(sizeof(int64_t) * (size_t)c));
         CK(hipStreamSynchronize(ctx->stream));
         CK(hipMemcpy(dn, nodes + j0, sizeof(int64_t) * c, hipMemcpyHostToDevice));
-        CK(launch_nodes(ctx->opt.precision, ctx->pop((int)(ctx->step & 1)), ctx->d_reps() + r, dn, c, dout,
+        CK(launch_nodes(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, dn, c, dout, ctx->aa_odd(),
                         ctx->stream));
         CK(hipStreamSynchronize(ctx->stream));
         CK(hipMemcpy(f + (size_t)j0 * Q, dout, sizeof(double) * Q * c, hipMemcpyDeviceToHost));
@@ -798,9 +829,11 @@ int gmf_get_step(gmf_ctx* ctx, int64_t* t)
     return GMF_OK;
 }
 
-int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int32_t* graphs, int32_t* addressing)
+int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int32_t* graphs, int32_t* addressing,
+                   int32_t* streaming)
 {
     if (!ctx) return GMF_ESTATE;
+    if (streaming) *streaming = ctx->aa ? GMF_STREAM_AA : GMF_STREAM_AB;
     if (nodes_per_thread) *nodes_per_thread = ctx->npt;
     if (block) *block = kBlock;
     if (graphs) *graphs = ctx->graph_steps;

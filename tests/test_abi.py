@@ -57,6 +57,11 @@ def test_workspace_bytes_and_validation():
     assert _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], precision=7) == 0
     assert _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], sample_every=-1) == 0
     assert _ws([(2048, 4096, 1, 1.0, 1.0, 1e-4, 1)], sample_every=10) == 0   # spectra LDS limit
+    assert _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], streaming=3) == 0           # unknown streaming pattern
+    # the in-place AA pattern needs one population buffer instead of two
+    aa = _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], streaming=gmf.STREAM_AA)
+    assert ok - aa >= 27 * 8 * 16 ** 3
+    assert _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], streaming=gmf.STREAM_AB) == ok
     # the 512^3 stress workload fits both precisions
     assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)]) > 2 * 27 * 8 * 512 ** 3
     assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)], precision=gmf.FP32_SHIFTED) > 0
