@@ -135,3 +135,43 @@ def test_tau_sweep_statistics_fp32_vs_fp64():
         if s.tau >= 1.0:
             flat = np.array([kbt / CS2, kbt, 3 * kbt, 5 * kbt, kbt])[:, None]
             assert abs(np.mean(sb / flat) - 1) < 0.05, (s.tau, sb / flat)
+
+
+def test_ensemble_workload_statistics_and_single_replica_bitwise():
+    """The batched ensemble: 32 replicas at 32^3, 16 at 48^3 and 16 at 64^3 with
+    the drawn taus, seeds 1..64, k_B T = 1e-4, 5000 steps sampled every 10, in
+    one context, FP32 shifted and FP64 plain.  Per replica (statistics after a
+    1000-step warm-up): the FP32/FP64 variance ratios are within 1% (paired
+    noise) and the FP64 variances of drho, j, u are at their equilibrium values;
+    one replica of each size equals its single-replica run bit for bit."""
+    w = wl.ensemble()
+    specs = [gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed) for b in w.boxes]
+    kbt = 1e-4
+    warm = 1000
+    picks = (0, 32, 48)
+    out, finals = {}, {}
+    for prec in (gmf.FP32_SHIFTED, gmf.FP64):
+        say(f"ensemble prec={prec}")
+        with gmf.Context(specs, precision=prec, sample_every=w.sample_every) as ctx:
+            ctx.step(warm)
+            ctx.reset_stats()
+            ctx.step(w.steps - warm)
+            out[prec] = [ctx.stats(r) for r in range(len(specs))]
+            finals[prec] = {r: ctx.get_populations(r) for r in picks}
+    for r in picks:
+        say(f"ensemble replica {r} alone")
+        with gmf.Context([specs[r]], precision=gmf.FP32_SHIFTED, sample_every=w.sample_every) as ctx:
+            ctx.step(w.steps)
+            assert np.array_equal(ctx.get_populations(), finals[gmf.FP32_SHIFTED][r]), r
+    worst = {}
+    for r, s in enumerate(specs):
+        a, b = out[gmf.FP32_SHIFTED][r], out[gmf.FP64][r]
+        assert a["nsamples"] == b["nsamples"] == (w.steps - warm) // w.sample_every
+        va, vb = a["sum_var"] / a["nsamples"], b["sum_var"] / b["nsamples"]
+        assert np.all(np.abs(va / vb - 1) < 0.01), (r, s.tau, va / vb)
+        theory = np.array([kbt / CS2, kbt, kbt, kbt, 3 * kbt, 5 * kbt, kbt, kbt, kbt, kbt]) * (1 - 1.0 / s.n)
+        er = vb / theory
+        tol = 0.03 if s.tau < 0.55 else 0.015
+        worst[r] = float(np.max(np.abs(er[[0, 1, 2, 3, 7, 8, 9]] - 1)))
+        assert worst[r] < tol, (r, s.nx, s.tau, np.round(er, 4))
+    say("ensemble worst |ER - 1| per replica: " + " ".join(f"{v:.4f}" for v in worst.values()))
