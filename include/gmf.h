@@ -119,7 +119,10 @@ typedef struct {
     int32_t graph_steps;  /* steps per captured HIP graph; 0: direct launches; < 0: default (64) */
     int32_t tune;         /* 0: built-in kernel configuration; 1: time the variants at init */
     int32_t streaming;    /* GMF_STREAM_AUTO, GMF_STREAM_AB or GMF_STREAM_AA */
-    int32_t reserved;     /* must be 0                                      */
+    int32_t spectrum;     /* 1: also accumulate the full-box shell spectra on every
+                             sampling step (needs sample_every > 0 and box lengths
+                             whose prime factors are 2, 3, 5, at most 1024 each;
+                             see gmf_spectrum); 0: off */
 } gmf_options;
 
 typedef struct {
@@ -167,8 +170,24 @@ int gmf_moments(gmf_ctx* ctx, int32_t r, double* rho, double* u);
  * GMF_EUNSTABLE (after filling *out) when a sampled density was not finite. */
 int gmf_stats(gmf_ctx* ctx, int32_t r, gmf_stats_t* out);
 
-/* Zero the sample accumulators of every replica. */
+/* Zero the sample accumulators of every replica (the full-box spectra too). */
 int gmf_reset_stats(gmf_ctx* ctx);
+
+/* Full-box shell spectra of replica r (Results section: structure factors
+ * from a normalised FFT of the whole box, averaged over shells of equal |k|).
+ * Needs options.spectrum = 1.  Shell s >= 1 holds the integer wave vectors n
+ * (k_a = 2 pi n_a / L_a, n_a in [-L_a/2, L_a/2)) with s - 1/2 <= |n| < s + 1/2;
+ * shell 0 (k = 0) stays empty.  On return:
+ *   sums[m * max_shells + s]  sum over the samples of the average of |m(k)|^2
+ *                             over shell s, m = GMF_SPEC_* (the same fields and
+ *                             normalisation as gmf_stats_t.spectrum);
+ *   counts[s]                 wave vectors in shell s;
+ *   *nshell                   shells of this replica (round(|n_max|) + 1).
+ * At most max_shells shells are written; any output pointer may be NULL
+ * (host memory, caller-owned).  The shell sums are exact integer sums of
+ * fixed-point terms, so a run reproduces its spectra bit for bit.
+ * Synchronises.  GMF_EINVAL if the option is off or r is out of range. */
+int gmf_spectrum(gmf_ctx* ctx, int32_t r, int32_t max_shells, double* sums, int64_t* counts, int32_t* nshell);
 
 /* Canonical populations f(x, t) of replica r (27*N FP64 values, host). */
 int gmf_get_populations(gmf_ctx* ctx, int32_t r, double* f);

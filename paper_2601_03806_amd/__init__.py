@@ -40,7 +40,7 @@ Q = 27
 EXPORTED = (
     "gmf_workspace_bytes", "gmf_init", "gmf_step", "gmf_moments", "gmf_stats", "gmf_reset_stats",
     "gmf_get_populations", "gmf_set_populations", "gmf_get_nodes", "gmf_get_step", "gmf_noise_probe",
-    "gmf_get_config", "gmf_copy_probe", "gmf_destroy", "gmf_strerror",
+    "gmf_get_config", "gmf_copy_probe", "gmf_destroy", "gmf_strerror", "gmf_spectrum",
 )
 
 
@@ -53,7 +53,7 @@ class Replica(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("collision", ctypes.c_int32), ("noise_rho", ctypes.c_int32),
                 ("sample_every", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("tune", ctypes.c_int32),
-                ("streaming", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("streaming", ctypes.c_int32), ("spectrum", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -102,6 +102,8 @@ def lib() -> ctypes.CDLL:
         L.gmf_noise_probe.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32), dp]
         L.gmf_get_config.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 5
+        L.gmf_spectrum.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp, ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_int32)]
         L.gmf_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.gmf_copy_probe.restype = ctypes.c_int
         L.gmf_destroy.argtypes = [vp]
@@ -110,7 +112,7 @@ def lib() -> ctypes.CDLL:
         L.gmf_strerror.restype = ctypes.c_char_p
         for name in ("gmf_init", "gmf_step", "gmf_moments", "gmf_stats", "gmf_reset_stats",
                      "gmf_get_populations", "gmf_set_populations", "gmf_get_nodes", "gmf_get_step",
-                     "gmf_noise_probe", "gmf_get_config"):
+                     "gmf_noise_probe", "gmf_get_config", "gmf_spectrum"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -153,11 +155,11 @@ def make_replicas(specs):
 
 
 def make_options(precision=FP64, collision=COLLISION_GMF, noise_rho=0, sample_every=0, graph_steps=-1, tune=0,
-                 streaming=STREAM_AUTO):
+                 streaming=STREAM_AUTO, spectrum=0):
     o = Options()
     o.precision, o.collision, o.noise_rho = precision, collision, noise_rho
     o.sample_every, o.graph_steps, o.tune = sample_every, graph_steps, tune
-    o.streaming = streaming
+    o.streaming, o.spectrum = streaming, spectrum
     return o
 
 
@@ -191,10 +193,11 @@ class Context:
     """
 
     def __init__(self, specs, *, precision=FP64, collision=COLLISION_GMF, noise_rho=0, sample_every=0,
-                 graph_steps=-1, tune=0, streaming=STREAM_AUTO, workspace="torch", stream=None):
+                 graph_steps=-1, tune=0, streaming=STREAM_AUTO, spectrum=0, workspace="torch", stream=None):
         self.specs = list(specs)
         self._reps = make_replicas(self.specs)
-        self._opt = make_options(precision, collision, noise_rho, sample_every, graph_steps, tune, streaming)
+        self._opt = make_options(precision, collision, noise_rho, sample_every, graph_steps, tune, streaming,
+                                 spectrum)
         self.precision = precision
         self._ws = None
         ws_ptr, ws_bytes = None, 0
@@ -276,6 +279,18 @@ class Context:
 
     def reset_stats(self):
         _check(lib().gmf_reset_stats(self._h), "gmf_reset_stats")
+
+    def spectrum(self, r: int = 0):
+        """Full-box shell spectra (needs spectrum=1): sums over the samples of the
+        shell averages, (5, nshell) in GMF_SPEC_* order, and the shell counts."""
+        ns = ctypes.c_int32()
+        _check(lib().gmf_spectrum(self._h, r, 0, None, None, ctypes.byref(ns)), "gmf_spectrum")
+        sums = np.zeros(NSPEC * ns.value)
+        counts = np.zeros(ns.value, np.int64)
+        rc = lib().gmf_spectrum(self._h, r, ns.value, _dp(sums), counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                ctypes.byref(ns))
+        _check(rc, "gmf_spectrum")
+        return sums.reshape(NSPEC, ns.value), counts
 
     def get_populations(self, r: int = 0) -> np.ndarray:
         f = np.zeros(Q * self.specs[r].n)

@@ -95,6 +95,10 @@ struct RepDev {
     double omega;             // 1 / tau
     double one_m_omega;       // 1 - omega
     double amp[8];            // noise amplitudes / sqrt(rho): groups of equal b_k (see host)
+    // full-box spectra (only when they are switched on)
+    uint64_t spec_offset;     // complex offset of the replica's three packed field transforms (3 N values)
+    uint32_t shell_offset;    // first shell record of the replica
+    uint32_t nshell;          // shells 0 .. nshell - 1 (shell 0 holds k = 0 only and stays empty)
 };
 
 // Planes per workgroup of the first shell-spectrum DFT stage: kBlock / nx for

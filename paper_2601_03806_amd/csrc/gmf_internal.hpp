@@ -43,7 +43,9 @@ hipError_t launch_init(int precision, void* buf, const RepDev* rep_dev, const Re
 // FP64 partials of the observables from the sampled fields: nrep * kObsChunks * kPartialStride doubles
 hipError_t launch_observables(int precision, const RepDev* reps, int32_t nrep, const void* fields, double* partials,
                               hipStream_t s);
-hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* partials, double* acc, hipStream_t s);
+// sample_sq (nullable): nrep * kObs sums over the box of each observable squared, for this sample
+hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* partials, double* acc,
+                               double* sample_sq, hipStream_t s);
 hipError_t launch_twiddles(const RepDev* reps, int32_t nrep, double2* tw, hipStream_t s);
 // dft: per replica kFields * nz * kDftPlane complex; zbuf: nrep * kFields * kZSplit * 196 complex
 // chunks: workgroups of the first DFT stage, (replica << 16) | chunk index;
@@ -51,6 +53,13 @@ hipError_t launch_twiddles(const RepDev* reps, int32_t nrep, double2* tw, hipStr
 hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint32_t* chunks, uint32_t nchunks,
                       const void* fields, const double2* tw, double2* dft, double2* zbuf, double* acc, size_t lds,
                       hipStream_t s);
+// full-box shell spectra of one sample (gmf_fft.hip): first = 4 prefix arrays of
+// nrep + 1 workgroup counts (passes x, y, z, binning), nblk their totals, lds
+// the dynamic LDS bytes of each of the four kernels
+hipError_t launch_spectrum(int precision, const RepDev* reps, int32_t nrep, const uint32_t* first, const uint32_t* nblk,
+                           const void* fields, const double2* tw, double2* spec, const double* sample_sq,
+                           const int64_t* counts, unsigned long long* bins, double* sacc, const size_t* lds,
+                           hipStream_t s);
 hipError_t launch_set_step(int64_t* d_step, int64_t value, hipStream_t s);
 hipError_t launch_advance_step(int64_t* d_step, int64_t by, hipStream_t s);
 

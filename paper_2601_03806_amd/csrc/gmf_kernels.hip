@@ -212,6 +212,9 @@ __device__ __forceinline__ RepDev uniform_rep(const RepDev& in)
     R.one_m_omega = sgprf(in.one_m_omega);
 #pragma unroll
     for (int g = 0; g < 8; ++g) R.amp[g] = sgprf(in.amp[g]);
+    R.spec_offset = sgpr64(in.spec_offset);
+    R.shell_offset = sgpr(in.shell_offset);
+    R.nshell = sgpr(in.nshell);
     return R;
 }
 
@@ -578,7 +581,7 @@ hipError_t launch_observables(int precision, const RepDev* reps, int32_t nrep, c
 // The kObsChunks partials of each replica, summed in a fixed order, update
 // the accumulators.
 __global__ __launch_bounds__(kBlock) void stats_accumulate_kernel(const RepDev* reps, const double* partials,
-                                                                  double* acc)
+                                                                  double* acc, double* sample_sq)
 {
     const RepDev& R = reps[blockIdx.x];
     constexpr int NV = 2 * kObs + 1;
@@ -603,12 +606,16 @@ __global__ __launch_bounds__(kBlock) void stats_accumulate_kernel(const RepDev* 
             A[kAccMeanSq + q] += m2;
             A[kAccVar + q] += m2 - m * m;
         }
+        // this sample's sums of squares (they bound the full-box spectra, see gmf_fft.hip)
+        if (sample_sq)
+            for (int q = 0; q < kObs; ++q) sample_sq[(size_t)blockIdx.x * kObs + q] = tot[2 * q + 1];
     }
 }
 
-hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* partials, double* acc, hipStream_t s)
+hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* partials, double* acc,
+                               double* sample_sq, hipStream_t s)
 {
-    stats_accumulate_kernel<<<nrep, kBlock, 0, s>>>(reps, partials, acc);
+    stats_accumulate_kernel<<<nrep, kBlock, 0, s>>>(reps, partials, acc, sample_sq);
     return hipGetLastError();
 }
 

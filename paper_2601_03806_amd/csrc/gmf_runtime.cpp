@@ -19,6 +19,7 @@
 
 #include "../../include/gmf.h"
 #include "gmf_device.hpp"
+#include "gmf_fft.hpp"
 #include "gmf_internal.hpp"
 
 using namespace gmf;
@@ -45,6 +46,13 @@ struct Layout {
     uint32_t total_chunks = 0;     // workgroups of the first spectrum stage
     size_t dft_lds = 0;
     size_t twiddles = 0, zbuf = 0;
+    size_t sample_sq = 0;          // per-sample sums of squares (sampling)
+    // full-box spectra (spectrum option)
+    bool spectrum = false;
+    size_t spec = 0, sbins = 0, sacc = 0, scounts = 0, sfirst = 0;
+    uint64_t nshell_total = 0;
+    uint32_t spec_blocks[4] = {0, 0, 0, 0};   // workgroups of the x, y, z passes and of the binning
+    size_t spec_lds[4] = {0, 0, 0, 0};
     uint32_t tw_complex = 0;
     uint64_t total_nodes = 0;
     uint32_t max_blocks = 0;     // lattice grid at one node per thread
@@ -84,6 +92,26 @@ int choose_mode(const gmf_replica* reps, int32_t nrep, uint64_t es, int npt)
     return -1;
 }
 
+// Integer wave vectors of an nx x ny x nz box in each shell s = round(|n|)
+// (s = 0 holds k = 0 only and is left empty); appends nshell counts.
+void count_shells(uint32_t nx, uint32_t ny, uint32_t nz, uint32_t nshell, std::vector<int64_t>& out)
+{
+    std::vector<int64_t> cnt(nshell, 0);
+    for (uint32_t z = 0; z < nz; ++z) {
+        const int64_t fz = signed_freq(z, nz);
+        for (uint32_t y = 0; y < ny; ++y) {
+            const int64_t fy = signed_freq(y, ny);
+            const int64_t c = fy * fy + fz * fz;
+            for (uint32_t x = 0; x < nx; ++x) {
+                const int64_t fx = signed_freq(x, nx);
+                const uint64_t n2 = (uint64_t)(fx * fx + c);
+                if (n2 > 0) cnt[shell_of(n2)] += 1;
+            }
+        }
+    }
+    out.insert(out.end(), cnt.begin(), cnt.end());
+}
+
 int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
 {
     if (!reps || nrep < 1 || nrep > 65535) return GMF_EINVAL;
@@ -92,8 +120,8 @@ int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         if (opt->collision != GMF_COLLISION_GMF && opt->collision != GMF_COLLISION_BGK) return GMF_EINVAL;
         if (opt->noise_rho != 0 && opt->noise_rho != 1) return GMF_EINVAL;
         if (opt->sample_every < 0 || opt->tune < 0 || opt->tune > 1) return GMF_EINVAL;
-        if (opt->streaming < GMF_STREAM_AUTO || opt->streaming > GMF_STREAM_AA || opt->reserved != 0)
-            return GMF_EINVAL;
+        if (opt->streaming < GMF_STREAM_AUTO || opt->streaming > GMF_STREAM_AA) return GMF_EINVAL;
+        if (opt->spectrum != 0 && (opt->spectrum != 1 || opt->sample_every <= 0)) return GMF_EINVAL;
     }
     const size_t es = (opt && opt->precision == GMF_FP32_SHIFTED) ? 4 : 8;
     const bool sampling = opt && opt->sample_every > 0;
@@ -107,6 +135,12 @@ int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         if (!std::isfinite(R.kbt) || R.kbt < 0.0) return GMF_EINVAL;
         // the first spectrum stage keeps twiddles and y-transformed columns in LDS
         if (sampling && dft_lds_bytes((uint32_t)R.nx, (uint32_t)R.ny) > 65536) return GMF_EINVAL;
+        // full-box spectra: line lengths with prime factors 2, 3, 5 only, at most kFftMaxLen
+        if (opt && opt->spectrum) {
+            FftPlan pl;
+            if (!fft_plan((uint32_t)R.nx, pl) || !fft_plan((uint32_t)R.ny, pl) || !fft_plan((uint32_t)R.nz, pl))
+                return GMF_EINVAL;
+        }
     }
     if (choose_mode(reps, nrep, es, 1) < 0) return GMF_EINVAL;
     return GMF_OK;
@@ -165,6 +199,27 @@ Layout plan(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         L.chunks = take(sizeof(uint32_t) * L.total_chunks);
         L.twiddles = take(sizeof(double) * 2 * L.tw_complex);
         L.zbuf = take(sizeof(double) * 2 * kFields * kZSplit * 196 * nrep);
+        L.sample_sq = take(sizeof(double) * kObs * nrep);
+    }
+    L.spectrum = L.sampling && opt->spectrum;
+    if (L.spectrum) {
+        for (int r = 0; r < nrep; ++r) {
+            const uint32_t nx = (uint32_t)reps[r].nx, ny = (uint32_t)reps[r].ny, nz = (uint32_t)reps[r].nz;
+            const uint32_t ns = box_shells(nx, ny, nz);
+            L.nshell_total += ns;
+            for (int a = 0; a < 3; ++a) {
+                L.spec_blocks[a] += fft_tiles(a, nx, ny, nz);
+                L.spec_lds[a] = std::max<size_t>(L.spec_lds[a], fft_lds_bytes(a, nx, ny, nz));
+            }
+            const uint64_t n = (uint64_t)nx * ny * nz;
+            L.spec_blocks[3] += (uint32_t)((n + kBinPoints - 1) / kBinPoints);
+            L.spec_lds[3] = std::max<size_t>(L.spec_lds[3], sizeof(unsigned long long) * kSpec * ns);
+        }
+        L.spec = take(sizeof(double) * 2 * kFftArrays * (size_t)L.total_nodes);
+        L.sbins = take(sizeof(unsigned long long) * kSpec * L.nshell_total);
+        L.sacc = take(sizeof(double) * kSpec * L.nshell_total);
+        L.scounts = take(sizeof(int64_t) * L.nshell_total);
+        L.sfirst = take(sizeof(uint32_t) * 4 * (nrep + 1));
     }
     L.stage = take(L.stage_bytes);
     L.total = off;
@@ -236,6 +291,12 @@ struct gmf_ctx {
     uint32_t* d_chunks() { return L.sampling ? reinterpret_cast<uint32_t*>(ws + L.chunks) : nullptr; }
     double2* d_twiddles() { return L.sampling ? reinterpret_cast<double2*>(ws + L.twiddles) : nullptr; }
     double2* d_zbuf() { return L.sampling ? reinterpret_cast<double2*>(ws + L.zbuf) : nullptr; }
+    double* d_sample_sq() { return L.sampling ? reinterpret_cast<double*>(ws + L.sample_sq) : nullptr; }
+    double2* d_spec() { return reinterpret_cast<double2*>(ws + L.spec); }
+    unsigned long long* d_sbins() { return reinterpret_cast<unsigned long long*>(ws + L.sbins); }
+    double* d_sacc() { return reinterpret_cast<double*>(ws + L.sacc); }
+    int64_t* d_scounts() { return reinterpret_cast<int64_t*>(ws + L.scounts); }
+    uint32_t* d_sfirst() { return reinterpret_cast<uint32_t*>(ws + L.sfirst); }
     char* d_stage() { return ws + L.stage; }
 };
 
@@ -304,10 +365,15 @@ int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
     if (sample) {
         CK(launch_observables(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_fields(), ctx->d_partials(),
                               ctx->stream));
-        CK(launch_stats_reduce(ctx->d_reps(), ctx->nrep, ctx->d_partials(), ctx->d_acc(), ctx->stream));
+        CK(launch_stats_reduce(ctx->d_reps(), ctx->nrep, ctx->d_partials(), ctx->d_acc(), ctx->d_sample_sq(),
+                               ctx->stream));
         CK(launch_dft(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_chunks(), ctx->L.total_chunks,
                       ctx->d_fields(), ctx->d_twiddles(), reinterpret_cast<double2*>(ctx->d_dft()), ctx->d_zbuf(),
                       ctx->d_acc(), ctx->L.dft_lds, ctx->stream));
+        if (ctx->L.spectrum)
+            CK(launch_spectrum(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_sfirst(), ctx->L.spec_blocks,
+                               ctx->d_fields(), ctx->d_twiddles(), ctx->d_spec(), ctx->d_sample_sq(),
+                               ctx->d_scounts(), ctx->d_sbins(), ctx->d_sacc(), ctx->L.spec_lds, ctx->stream));
     }
     return GMF_OK;
 }
@@ -565,9 +631,11 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
     ctx->grp = ctx->mode == 0 ? 27 : ctx->mode;
     ctx->aa = opt.streaming == GMF_STREAM_AA;
     // replica records
-    uint64_t pop_off = 0, field_off = 0;
-    uint32_t dft_off = 0, tw_off = 0;
+    uint64_t pop_off = 0, field_off = 0, spec_off = 0;
+    uint32_t dft_off = 0, tw_off = 0, shell_off = 0;
     std::vector<uint32_t> chunks;
+    std::vector<int64_t> shell_counts;
+    std::vector<uint32_t> spec_first(L.spectrum ? 4 * (size_t)(nrep + 1) : 0, 0u);
     for (int r = 0; r < nrep; ++r) {
         const gmf_replica& in = reps[r];
         RepDev R;
@@ -601,6 +669,19 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
             const bool hydro = g < 2 || opt.collision == GMF_COLLISION_BGK;
             R.amp[g] = std::sqrt(in.kbt * (hydro ? relax : 1.0) * kGroupB[g] / kCs2);
         }
+        if (L.spectrum) {
+            R.spec_offset = spec_off;
+            R.shell_offset = shell_off;
+            R.nshell = box_shells(R.nx, R.ny, R.nz);
+            spec_off += (uint64_t)kFftArrays * R.n;
+            shell_off += R.nshell;
+            count_shells(R.nx, R.ny, R.nz, R.nshell, shell_counts);
+            for (int a = 0; a < 3; ++a)
+                spec_first[(size_t)a * (nrep + 1) + r + 1] =
+                    spec_first[(size_t)a * (nrep + 1) + r] + fft_tiles(a, R.nx, R.ny, R.nz);
+            spec_first[3 * (size_t)(nrep + 1) + r + 1] =
+                spec_first[3 * (size_t)(nrep + 1) + r] + (R.n + kBinPoints - 1) / kBinPoints;
+        }
         ctx->rdev.push_back(R);
         if (L.sampling) {
             const uint32_t P = dft_planes_per_block(R.nx);
@@ -610,6 +691,13 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
     if (L.sampling) {
         hipError_t e = hipMemcpy(ctx->d_chunks(), chunks.data(), sizeof(uint32_t) * chunks.size(),
                                  hipMemcpyHostToDevice);
+        if (e == hipSuccess && L.spectrum) {
+            e = hipMemcpy(ctx->d_scounts(), shell_counts.data(), sizeof(int64_t) * shell_counts.size(),
+                          hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(ctx->d_sfirst(), spec_first.data(), sizeof(uint32_t) * spec_first.size(),
+                              hipMemcpyHostToDevice);
+        }
         if (e != hipSuccess) {
             gmf_destroy(ctx);
             return GMF_EDEVICE;
@@ -641,6 +729,10 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         return rc;
     }
     if (hipMemsetAsync(ctx->d_acc(), 0, sizeof(double) * kAccStride * nrep, ctx->stream) != hipSuccess ||
+        (L.spectrum &&
+         (hipMemsetAsync(ctx->d_sbins(), 0, sizeof(unsigned long long) * kSpec * L.nshell_total, ctx->stream) !=
+              hipSuccess ||
+          hipMemsetAsync(ctx->d_sacc(), 0, sizeof(double) * kSpec * L.nshell_total, ctx->stream) != hipSuccess)) ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
         gmf_destroy(ctx);
         return GMF_EDEVICE;
@@ -743,7 +835,33 @@ int gmf_reset_stats(gmf_ctx* ctx)
     if (rc != GMF_OK) return rc;
     DeviceGuard g(ctx->device);
     CK(hipMemsetAsync(ctx->d_acc(), 0, sizeof(double) * kAccStride * ctx->nrep, ctx->stream));
+    if (ctx->L.spectrum) {
+        CK(hipMemsetAsync(ctx->d_sacc(), 0, sizeof(double) * kSpec * ctx->L.nshell_total, ctx->stream));
+        CK(hipMemsetAsync(ctx->d_sbins(), 0, sizeof(unsigned long long) * kSpec * ctx->L.nshell_total, ctx->stream));
+    }
     CK(hipStreamSynchronize(ctx->stream));
+    return GMF_OK;
+}
+
+int gmf_spectrum(gmf_ctx* ctx, int32_t r, int32_t max_shells, double* sums, int64_t* counts, int32_t* nshell)
+{
+    int rc = check_ctx(ctx);
+    if (rc != GMF_OK) return rc;
+    if (r < 0 || r >= ctx->nrep || max_shells < 0 || !ctx->L.spectrum) return GMF_EINVAL;
+    DeviceGuard g(ctx->device);
+    const RepDev& R = ctx->rdev[r];
+    if (nshell) *nshell = (int32_t)R.nshell;
+    const uint32_t ns = std::min<uint32_t>(R.nshell, (uint32_t)max_shells);
+    CK(hipStreamSynchronize(ctx->stream));
+    if (sums && ns > 0) {
+        std::vector<double> rec((size_t)kSpec * R.nshell);
+        CK(hipMemcpy(rec.data(), ctx->d_sacc() + (size_t)R.shell_offset * kSpec, sizeof(double) * rec.size(),
+                     hipMemcpyDeviceToHost));
+        for (int m = 0; m < kSpec; ++m)
+            for (uint32_t s2 = 0; s2 < ns; ++s2) sums[(size_t)m * max_shells + s2] = rec[(size_t)s2 * kSpec + m];
+    }
+    if (counts && ns > 0)
+        CK(hipMemcpy(counts, ctx->d_scounts() + R.shell_offset, sizeof(int64_t) * ns, hipMemcpyDeviceToHost));
     return GMF_OK;
 }
 

@@ -62,6 +62,14 @@ def test_workspace_bytes_and_validation():
     aa = _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], streaming=gmf.STREAM_AA)
     assert ok - aa >= 27 * 8 * 16 ** 3
     assert _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], streaming=gmf.STREAM_AB) == ok
+    # full-box spectra: need sampling and box lengths with prime factors 2, 3, 5 (at most 1024)
+    base = _ws([(12, 10, 8, 1.0, 1.0, 1e-4, 1)], sample_every=5)
+    with_spec = _ws([(12, 10, 8, 1.0, 1.0, 1e-4, 1)], sample_every=5, spectrum=1)
+    assert with_spec >= base + 3 * 16 * 960
+    assert _ws([(12, 10, 8, 1.0, 1.0, 1e-4, 1)], spectrum=1) == 0                  # no sampling
+    assert _ws([(14, 10, 8, 1.0, 1.0, 1e-4, 1)], sample_every=5, spectrum=1) == 0  # factor 7
+    assert _ws([(2048, 8, 8, 1.0, 1.0, 1e-4, 1)], sample_every=5, spectrum=1) == 0  # longer than 1024
+    assert _ws([(12, 10, 8, 1.0, 1.0, 1e-4, 1)], sample_every=5, spectrum=2) == 0
     # the 512^3 stress workload fits both precisions
     assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)]) > 2 * 27 * 8 * 512 ** 3
     assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)], precision=gmf.FP32_SHIFTED) > 0

@@ -1,0 +1,122 @@
+"""Full-box shell spectra on the device against the oracle's FFT reference
+(oracle/spectrum.py): per sample, the oracle transforms the canonical state
+that the library holds at the sampled step; the library's accumulated shell
+averages must equal the oracle's sums over the same samples.  Also: the
+integer shell sums make the spectra reproducible bit for bit (graph against
+direct launches, batched against single replicas), and the equilibrium
+spectra of a 64^3 box are flat at their fluctuation-dissipation values."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import spectrum as sp
+import paper_2601_03806_amd as gmf
+from paper_2601_03806_amd import workloads as wl
+from gpu_common import oracle_params, say
+
+pytestmark = pytest.mark.gpu
+
+CS2 = 1.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def w():
+    return oracle.tables()[1]
+
+
+def _sampled_run(specs, prec, every, nsamples, f0s=None, graph_steps=0):
+    """Sample at t = 0, every, 2 every, ...; return the library's spectra and
+    the canonical states at the sampled steps."""
+    states = [[] for _ in specs]
+    with gmf.Context(specs, precision=prec, sample_every=every, spectrum=1, graph_steps=graph_steps) as ctx:
+        if f0s is not None:
+            for r, f0 in enumerate(f0s):
+                ctx.set_populations(f0, r)
+        for _ in range(nsamples):
+            for r in range(len(specs)):
+                states[r].append(ctx.get_populations(r))
+            ctx.step(every)
+        st = [ctx.stats(r) for r in range(len(specs))]
+        out = [ctx.spectrum(r) for r in range(len(specs))]
+    for s in st:
+        assert s["nsamples"] == nsamples
+    return out, states
+
+
+def _oracle_sums(spec, prec, states):
+    p = oracle_params(spec, precision=prec)
+    tot = None
+    for f in states:
+        s, cnt = sp.full_spectrum(p, f)
+        tot = s if tot is None else tot + s
+    return tot, cnt
+
+
+@pytest.mark.parametrize("prec,rtol", [(gmf.FP64, 1e-12), (gmf.FP32_SHIFTED, 1e-6)])
+def test_full_spectrum_matches_oracle(w, prec, rtol):
+    specs = [gmf.ReplicaSpec(12, 10, 8, 1.0, 0.7, 1e-4, 3), gmf.ReplicaSpec(16, 4, 2, 1.0, 1.3, 1e-4, 4),
+             gmf.ReplicaSpec(5, 6, 3, 1.0, 0.55, 1e-4, 5), gmf.ReplicaSpec(1, 8, 4, 1.0, 2.0, 1e-4, 6)]
+    f0s = [wl.perturbed_populations(w, s.n, amp=0.03, seed=10 + r, velocity=0.03) for r, s in enumerate(specs)]
+    say(f"full spectrum vs oracle prec={prec}")
+    out, states = _sampled_run(specs, prec, 5, 5, f0s)
+    for r, s in enumerate(specs):
+        got, cnt = out[r]
+        ref, rcnt = _oracle_sums(s, prec, states[r])
+        assert np.array_equal(cnt, rcnt), r
+        scale = np.max(np.abs(ref), axis=1, keepdims=True)
+        err = np.max(np.abs(got - ref) / scale)
+        say(f"  replica {r} {s.nx}x{s.ny}x{s.nz}: max rel err {err:.2e}")
+        assert err < rtol, (r, err)
+
+
+def test_full_spectrum_bitwise_graph_and_batched():
+    specs = [gmf.ReplicaSpec(12, 10, 8, 1.0, 0.7, 1e-4, 3), gmf.ReplicaSpec(20, 9, 6, 1.0, 0.9, 1e-4, 8)]
+    res = {}
+    for gs in (0, 10):
+        say(f"full spectrum graph={gs}")
+        with gmf.Context(specs, precision=gmf.FP32_SHIFTED, sample_every=5, spectrum=1, graph_steps=gs) as ctx:
+            ctx.step(40)
+            res[gs] = [ctx.spectrum(r)[0] for r in range(2)]
+    for r in range(2):
+        assert np.array_equal(res[0][r], res[10][r]), r
+    for r, s in enumerate(specs):
+        with gmf.Context([s], precision=gmf.FP32_SHIFTED, sample_every=5, spectrum=1) as ctx:
+            ctx.step(40)
+            assert np.array_equal(ctx.spectrum()[0], res[0][r]), r
+    # reset clears them
+    with gmf.Context(specs, precision=gmf.FP32_SHIFTED, sample_every=5, spectrum=1) as ctx:
+        ctx.step(10)
+        ctx.reset_stats()
+        assert not np.any(ctx.spectrum(1)[0])
+
+
+def test_spectrum_option_errors():
+    with gmf.Context([gmf.ReplicaSpec(8, 8, 8, 1.0, 1.0, 1e-4, 1)], sample_every=5) as ctx:
+        with pytest.raises(gmf.GmfError):
+            ctx.spectrum()
+
+
+@pytest.mark.slow
+def test_equilibrium_spectra_are_flat():
+    """64^3, tau 1, k_B T 1e-4: after 2000 warm-up steps, 1000 samples (every
+    10 steps) of the shell spectra equal the equilibrium values rho0 k_BT / cs2
+    (density), rho0 k_BT (j), 3 rho0 k_BT (jsum), 5 rho0 k_BT (pdiag) and
+    rho0 k_BT (poff) at every shell s = 4 .. 32 within 3%, and on average
+    within 1%."""
+    kbt = 1e-4
+    spec = gmf.ReplicaSpec(64, 64, 64, 1.0, 1.0, kbt, 1)
+    flat = np.array([kbt / CS2, kbt, 3 * kbt, 5 * kbt, kbt])[:, None]
+    for prec in (gmf.FP32_SHIFTED, gmf.FP64):
+        say(f"equilibrium spectra prec={prec}")
+        with gmf.Context([spec], precision=prec, sample_every=10, spectrum=1) as ctx:
+            ctx.step(2000)
+            ctx.reset_stats()
+            ctx.step(10000)
+            nsamp = ctx.stats()["nsamples"]
+            sums, cnt = ctx.spectrum()
+        er = sums[:, 4:33] / nsamp / flat
+        say("  ER mean per spectrum " + " ".join(f"{v:.4f}" for v in er.mean(axis=1)) +
+            f"; worst shell {np.max(np.abs(er - 1)):.4f}")
+        assert nsamp == 1000
+        assert np.all(np.abs(er - 1) < 0.03)
+        assert np.all(np.abs(er.mean(axis=1) - 1) < 0.01)
