@@ -120,3 +120,24 @@ def test_equilibrium_spectra_are_flat():
         assert nsamp == 1000
         assert np.all(np.abs(er - 1) < 0.03)
         assert np.all(np.abs(er.mean(axis=1) - 1) < 0.01)
+
+
+@pytest.mark.parametrize("box,prec,rtol", [((96, 64, 80), gmf.FP32_SHIFTED, 1e-6), ((60, 72, 50), gmf.FP64, 1e-12),
+                                           ((256, 256, 256), gmf.FP32_SHIFTED, 1e-6)])
+def test_full_spectrum_large_boxes(box, prec, rtol):
+    """Mixed-radix lines (96 = 4 4 2 3, 80 = 4 4 5, 60, 72, 50) and the 256^3
+    headline box, one sample of the equilibrating fluid 40 steps from rest,
+    against the oracle's FFT of the same state."""
+    spec = gmf.ReplicaSpec(*box, 1.0, 0.8, 1e-4, 1)
+    say(f"full spectrum {box} prec={prec}")
+    with gmf.Context([spec], precision=prec, sample_every=20, spectrum=1) as ctx:
+        ctx.step(40)                      # samples t = 0 and 20
+        ctx.reset_stats()
+        f40 = ctx.get_populations()
+        ctx.step(1)                       # samples t = 40
+        got, cnt = ctx.spectrum()
+    ref, rcnt = sp.full_spectrum(oracle_params(spec, precision=prec), f40)
+    assert np.array_equal(cnt, rcnt)
+    err = np.max(np.abs(got - ref) / np.max(np.abs(ref), axis=1, keepdims=True))
+    say(f"  max rel err {err:.2e}")
+    assert err < rtol
