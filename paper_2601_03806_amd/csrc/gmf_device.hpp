@@ -95,11 +95,23 @@ struct RepDev {
     double omega;             // 1 / tau
     double one_m_omega;       // 1 - omega
     double amp[8];            // noise amplitudes / sqrt(rho): groups of equal b_k (see host)
+    // the same parameters rounded to binary32 once, for the FP32 kernels
+    float rho0f, omegaf, one_m_omegaf, padf;
+    float ampf[8];
     // full-box spectra (only when they are switched on)
     uint64_t spec_offset;     // complex offset of the replica's three packed field transforms (3 N values)
     uint32_t shell_offset;    // first shell record of the replica
     uint32_t nshell;          // shells 0 .. nshell - 1 (shell 0 holds k = 0 only and stays empty)
 };
+
+// A replica parameter in the kernel's precision: the double field for FP64,
+// its binary32 copy for FP32 (no per-thread conversion).
+template <typename T>
+__host__ __device__ inline T rep_param(double d, float f);
+template <>
+__host__ __device__ inline double rep_param<double>(double d, float) { return d; }
+template <>
+__host__ __device__ inline float rep_param<float>(double, float f) { return f; }
 
 // Planes per workgroup of the first shell-spectrum DFT stage: kBlock / nx for
 // nx <= kBlock (one column per thread), else 1 (threads loop over columns).

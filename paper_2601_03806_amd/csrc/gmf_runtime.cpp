@@ -668,7 +668,11 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         for (int g = 0; g < 8; ++g) {
             const bool hydro = g < 2 || opt.collision == GMF_COLLISION_BGK;
             R.amp[g] = std::sqrt(in.kbt * (hydro ? relax : 1.0) * kGroupB[g] / kCs2);
+            R.ampf[g] = (float)R.amp[g];
         }
+        R.rho0f = (float)R.rho0;
+        R.omegaf = (float)R.omega;
+        R.one_m_omegaf = (float)R.one_m_omega;
         if (L.spectrum) {
             R.spec_offset = spec_off;
             R.shell_offset = shell_off;
