@@ -36,9 +36,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_key: str, nodes: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+def variant_key(cfg: dict) -> str:
+    """Step-kernel variant as named in profiles/traffic.json."""
+    return f"{cfg['addressing']}/{cfg['streaming']}/npt{cfg['nodes_per_thread']}"
+
+
+def measured_traffic(kernel_key: str, nodes: int, cfg: dict):
+    """HBM bytes per launch of the step-kernel variant that ran, from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel
+    source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -48,7 +54,8 @@ def measured_traffic(kernel_key: str, nodes: int):
     ent = data.get(kernel_key)
     if not ent or ent.get("source_hash") != kernel_source_hash() or ent.get("nodes") != nodes:
         return None
-    return ent.get("bytes_per_launch")
+    var = ent.get("variants", {}).get(variant_key(cfg))
+    return None if var is None else var.get("bytes_per_launch")
 
 
 def time_context(ctx, stream, steps, warmup, torch):
@@ -228,7 +235,7 @@ def main():
                    "kernel_config": r32["config"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("step_fp32_256", r32["nodes"])},
+                     "traffic": measured_traffic("step_fp32_256", r32["nodes"], r32["config"])},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "mass_drift_rel": r32["mass_drift_rel"],
     }

@@ -1130,14 +1130,20 @@ hipError_t launch_noise_probe(int precision, uint64_t seed, int64_t t, uint32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Streaming copy (16-byte accesses, grid-stride): the practical bandwidth
-// reference the step kernel is compared with.
+// Streaming copy (16-byte nontemporal accesses, one per thread up to 2^28
+// threads, grid-stride beyond): the practical bandwidth reference the step
+// kernel is compared with.  Of the copy forms measured on MI355X (cached or
+// nontemporal, 1 to 8 vectors per thread, grid-stride), this one was fastest.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
                                                       uint64_t n4)
 {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const v4f* s = reinterpret_cast<const v4f*>(src);
+    v4f* d = reinterpret_cast<v4f*>(dst);
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += stride) dst[i] = src[i];
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(s + i), d + i);
 }
 
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s)
