@@ -175,3 +175,40 @@ def test_ensemble_workload_statistics_and_single_replica_bitwise():
         worst[r] = float(np.max(np.abs(er[[0, 1, 2, 3, 7, 8, 9]] - 1)))
         assert worst[r] < tol, (r, s.nx, s.tau, np.round(er, 4))
     say("ensemble worst |ER - 1| per replica: " + " ".join(f"{v:.4f}" for v in worst.values()))
+
+
+@pytest.mark.slow
+def test_gmf_keeps_equilibrium_where_bgk_departs():
+    """Results section: close to the stability limit the BGK-FLBM departs from
+    equilibrium, most in the momentum and off-diagonal stress, while GMF-FLBM
+    stays close to ER = 1.  64^3, k_BT 1e-4, FP64, tau = 0.505 (and tau = 1,
+    where both agree), 4000 warm-up + 40000 steps sampled every 10, full-box
+    spectra on shells 4..32."""
+    kbt = 1e-4
+    taus = (0.505, 1.0)
+    specs = [gmf.ReplicaSpec(64, 64, 64, 1.0, t, kbt, 1 + i) for i, t in enumerate(taus)]
+    N = specs[0].n
+    theory = np.array([kbt / CS2, kbt, kbt, kbt, 3 * kbt, 5 * kbt, kbt, kbt, kbt, kbt]) * (1 - 1.0 / N)
+    flat = np.array([kbt / CS2, kbt, 3 * kbt, 5 * kbt, kbt])[:, None]
+    res = {}
+    for coll in (gmf.COLLISION_GMF, gmf.COLLISION_BGK):
+        say(f"GMF vs BGK collision={coll}")
+        with gmf.Context(specs, precision=gmf.FP64, collision=coll, sample_every=10, spectrum=1) as ctx:
+            ctx.step(4000)
+            ctx.reset_stats()
+            ctx.step(40000)
+            for r, t in enumerate(taus):
+                st = ctx.stats(r)
+                er = st["sum_var"] / st["nsamples"] / theory
+                sums, _ = ctx.spectrum(r)
+                spec_er = sums[:, 4:33] / st["nsamples"] / flat
+                res[(coll, t)] = (er, spec_er)
+                say(f"  tau={t}: ER drho {er[0]:.4f} jsum {er[4]:.4f} pdiag {er[5]:.4f} poff {er[6]:.4f}; "
+                    f"spectral ER of j {spec_er[1].min():.3f}..{spec_er[1].max():.3f}")
+    idx = [0, 4, 5, 6]                                  # drho, jsum, pdiag, poff
+    g, b = res[(gmf.COLLISION_GMF, 0.505)], res[(gmf.COLLISION_BGK, 0.505)]
+    assert np.all(np.abs(g[0][idx] - 1) < 0.006), g[0]
+    assert np.abs(b[0][4] - 1) > 0.01 and np.abs(b[0][6] - 1) > 0.01, b[0]      # momentum, off-diagonal stress
+    assert np.min(g[1][1]) > 0.98 and np.min(b[1][1]) < 0.95                   # shells of the momentum spectrum
+    for coll in (gmf.COLLISION_GMF, gmf.COLLISION_BGK):
+        assert np.all(np.abs(res[(coll, 1.0)][0][idx] - 1) < 0.003)
