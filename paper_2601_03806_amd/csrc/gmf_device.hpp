@@ -123,14 +123,7 @@ __host__ __device__ inline uint64_t dft_lds_bytes(uint32_t nx, uint32_t ny)
 }
 
 // Element offset (inside the replica block) of the start of population p's
-// row at (y, z) = (0, 0): uniform per population, added to the base pointer.
-// The step kernel instantiates the group size G at compile time.
-template <int G>
-__host__ __device__ inline uint64_t pop_base_offset_g(const RepDev& R, int p)
-{
-    const uint32_t s = (uint32_t)slot_of(p);
-    return (uint64_t)(s / G) * R.grp_elems + (uint64_t)(s % G) * R.nx;
-}
+// row at (y, z) = (0, 0).
 __host__ __device__ inline uint64_t pop_base_offset(const RepDev& R, int p)
 {
     const uint32_t s = (uint32_t)slot_of(p);

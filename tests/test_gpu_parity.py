@@ -53,7 +53,7 @@ def test_noise_normals_fp64_and_fp32():
     _, r32 = gmf.noise_probe(5, 123, 77, 2000, gmf.FP32_SHIFTED)
     ref64 = np.array([oracle.normals(5, 77 + j, 123, 32)[4:] for j in range(2000)])
     ref23 = np.array([oracle.normals(5, 77 + j, 123, 23)[4:] for j in range(2000)])
-    # FP64: libm vs device log/sincospi differ in the last bits only
+    # FP64: the oracle's libm and the library's own log and sin/cos differ in the last bits only
     assert np.max(np.abs(r64 - ref64)) < 1e-13
     # FP32: the same uniforms, hardware transcendentals
     assert np.max(np.abs(r32 - ref23)) < 5e-5 * np.max(np.abs(ref23))
