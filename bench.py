@@ -213,7 +213,10 @@ def main():
     r32 = res["fp32"]
     glups = r32["nodes"] * r32["steps"] / r32["seconds"] / 1e9
     ms = r32["seconds"] / r32["steps"] * 1e3
-    kernel_s = r32["seconds"] / r32["steps"]   # step kernel duration per launch (graph replays)
+    # roofline of the step kernel: algorithmic bytes per launch over its average
+    # launch duration, i.e. the events around the timed region over its launches
+    # (the captured step loop launches the step kernel back to back)
+    kernel_s = r32["seconds"] / r32["steps"]
     achieved = BYTES_PER_NODE["fp32"] * r32["nodes"] / kernel_s / 1e9
     line = {
         "metric": METRIC,
