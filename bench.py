@@ -163,21 +163,33 @@ def copy_probe(torch, gmf, gbytes=1.812, reps=20):
     return {"bytes_read_plus_written": 2 * 4 * n, "seconds": sec, "gbs": 2 * 4 * n / sec / 1e9}
 
 
-def cpu_baseline(target_seconds=15.0):
+def cpu_baseline(target_seconds=12.0):
+    """The FP64 oracle as written, on the host: OpenMP over z planes on every
+    thread it gets (the reported value), then the same on one thread."""
     import oracle
     L = 16
     p = oracle.params(L, rho0=1.0, tau=1.0, kbt=1e-4, seed=1)
-    f = oracle.rest_state(p)
-    t0 = time.perf_counter()
-    oracle.run(p, f, 0, 5)
-    dt = time.perf_counter() - t0
-    steps = max(5, int(target_seconds / max(dt / 5, 1e-6)))
-    t0 = time.perf_counter()
-    oracle.run(p, f, 5, steps)
-    dt = time.perf_counter() - t0
-    glups = L ** 3 * steps / dt / 1e9
-    return {"value": glups, "unit": "GLUPS", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"16^3 FP64 GMF-FLBM (tau=1, kbt=1e-4, seed 1), {steps} steps ({dt:.1f} s)"}
+
+    def rate(seconds):
+        f = oracle.rest_state(p)
+        t0 = time.perf_counter()
+        oracle.run(p, f, 0, 5)
+        dt = time.perf_counter() - t0
+        steps = max(5, int(seconds / max(dt / 5, 1e-6)))
+        t0 = time.perf_counter()
+        oracle.run(p, f, 5, steps)
+        dt = time.perf_counter() - t0
+        return L ** 3 * steps / dt / 1e9, steps, dt
+
+    threads = oracle.num_threads()
+    glups, steps, dt = rate(target_seconds)
+    oracle.set_threads(1)
+    glups1, steps1, dt1 = rate(target_seconds / 3)
+    oracle.set_threads(threads)
+    return {"value": glups, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"16^3 FP64 GMF-FLBM (tau=1, kbt=1e-4, seed 1), {steps} steps ({dt:.1f} s) on {threads} threads; "
+                      f"single thread {glups1:.3g} GLUPS ({steps1} steps, {dt1:.1f} s)",
+            "value_single_thread": glups1}
 
 
 def main():

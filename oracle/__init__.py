@@ -186,3 +186,8 @@ def observables(p: Params, f: np.ndarray):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loop (timing only; results do not depend on it)."""
+    lib().oracle_set_threads(int(n))

@@ -588,6 +588,17 @@ void oracle_tables(int32_t *vel, double *w, double *e, double *b, int32_t *nk, i
     }
 }
 
+/* Threads of the OpenMP loop over z planes in oracle_run (timing only; the
+ * result does not depend on it). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

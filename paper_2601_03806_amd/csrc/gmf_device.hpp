@@ -116,11 +116,6 @@ __host__ __device__ inline float rep_param<float>(double, float f) { return f; }
 // Planes per workgroup of the first shell-spectrum DFT stage: kBlock / nx for
 // nx <= kBlock (one column per thread), else 1 (threads loop over columns).
 __host__ __device__ inline uint32_t dft_planes_per_block(uint32_t nx) { return nx <= (uint32_t)kBlock ? kBlock / nx : 1u; }
-// Dynamic LDS of that stage: y and x twiddles and the y-transformed columns.
-__host__ __device__ inline uint64_t dft_lds_bytes(uint32_t nx, uint32_t ny)
-{
-    return 16ull * (ny + nx + 4ull * dft_planes_per_block(nx) * nx);
-}
 
 // Element offset (inside the replica block) of the start of population p's
 // row at (y, z) = (0, 0).

@@ -48,11 +48,9 @@ hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* p
                                double* sample_sq, hipStream_t s);
 hipError_t launch_twiddles(const RepDev* reps, int32_t nrep, double2* tw, hipStream_t s);
 // dft: per replica kFields * nz * kDftPlane complex; zbuf: nrep * kFields * kZSplit * 196 complex
-// chunks: workgroups of the first DFT stage, (replica << 16) | chunk index;
-// lds: dynamic LDS bytes = 16 (ny + nx + 4 P nx), maximised over the replicas
+// chunks: workgroups of the first DFT stage, (replica << 16) | chunk index
 hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint32_t* chunks, uint32_t nchunks,
-                      const void* fields, const double2* tw, double2* dft, double2* zbuf, double* acc, size_t lds,
-                      hipStream_t s);
+                      const void* fields, const double2* tw, double2* dft, double2* zbuf, double* acc, hipStream_t s);
 // full-box shell spectra of one sample (gmf_fft.hip): first = 4 prefix arrays of
 // nrep + 1 workgroup counts (passes x, y, z, binning), nblk their totals, lds
 // the dynamic LDS bytes of each of the four kernels

@@ -642,12 +642,12 @@ hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* p
 // ---------------------------------------------------------------------------
 // Shell spectra (normalised DFT at the vectors of the shells |n|^2 in
 // {1,2,3,4,5,6,8,9}).  A real field has |m(-k)| = |m(k)|, so only n_x >= 0 is
-// computed and n_x > 0 counts twice.  Twiddles e^{-2 pi i m / L} for the three
+// computed and n_x > 0 counts twice.  Twiddles e^{2 pi i m / L} for the three
 // box lengths of each replica are tabulated once (twiddle_kernel).
-//   Stage 1 (one workgroup per (z plane, field)): one row per thread, DFT along
-//     x at n_x = 0..3 (the twiddle index is the same for every lane), then the
-//     DFT along y at n_y = -3..3 from the rows kept in LDS.
-//   Stage 2 (one workgroup per (replica, field)): DFT along z at n_z = -3..3.
+//   Stage 1 (workgroups of z planes, per field): DFT along y at n_y = 0..3,
+//     one column per thread (Y(-n_y) = conj Y(n_y)), then along x at
+//     n_x = 0..3 from the columns kept in LDS.
+//   Stage 2 (per replica, field and z chunk): DFT along z at n_z = -3..3.
 //   Stage 3 (one workgroup per replica): powers of the five spectra, shell
 //     averages into the accumulators (fixed summation order).
 // ---------------------------------------------------------------------------
@@ -672,12 +672,38 @@ hipError_t launch_twiddles(const RepDev* reps, int32_t nrep, double2* tw, hipStr
     return hipGetLastError();
 }
 
+// Partial x-transform of item o = (n_x, n_y) over columns xb .. xe - 1 whose
+// y-transforms Y[x - xb][0..3] are in Yp: sum_x Y_{n_y}(x) e^{-2 pi i n_x x / nx},
+// with Y_{-n_y} = conj(Y_{n_y}).  twx[m] = e^{2 pi i m / nx}.
+__device__ __forceinline__ double2 dft_x_item(const double2* Yp, const double2* twx, uint32_t nx, uint32_t xb,
+                                              uint32_t xe, uint32_t o)
+{
+    const uint32_t q = o / kDftNy;
+    const int sy = (int)(o % kDftNy) - 3;
+    const uint32_t ay = (uint32_t)(sy < 0 ? -sy : sy);
+    const double sg = sy < 0 ? -1.0 : 1.0;          // conjugate for negative n_y
+    double re = 0.0, im = 0.0;
+    uint32_t m = (uint32_t)(((uint64_t)q * xb) % nx);
+    for (uint32_t x = xb; x < xe; ++x) {
+        const double2 yv = Yp[(uint64_t)(x - xb) * 4 + ay];
+        const double yr = yv.x, yi = sg * yv.y;
+        const double2 t = twx[m];
+        // (yr + i yi)(c - i s)
+        re += yr * t.x + yi * t.y;
+        im += yi * t.x - yr * t.y;
+        m += q;
+        while (m >= nx) m -= nx;
+    }
+    return make_double2(re, im);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void dft_plane_kernel(const RepDev* reps, const uint32_t* chunks,
                                                            const T* __restrict__ fields,
                                                            const double2* __restrict__ tw, double2* dft)
 {
-    extern __shared__ double2 lds[];    // y twiddles (ny), x twiddles (nx), Y[plane][x][n_y = 0..3]
+    // Y[column][n_y = 0..3] of up to kBlock columns (one per thread)
+    __shared__ double2 Ys[kBlock * 4];
     const uint32_t ck = chunks[blockIdx.x];
     const int fld = blockIdx.y;
     const int r = (int)(ck >> 16);
@@ -685,72 +711,70 @@ __global__ __launch_bounds__(kBlock) void dft_plane_kernel(const RepDev* reps, c
     const uint32_t nx = R.nx, ny = R.ny, nz = R.nz;
     const uint32_t P = dft_planes_per_block(nx);
     const uint32_t z0 = (ck & 0xffffu) * P;
-    double2* twy_s = lds;
-    double2* twx_s = lds + ny;
-    double2* Ys = lds + ny + nx;
-    const double2* twg = tw + R.tw_offset;
-    for (uint32_t m = threadIdx.x; m < nx + ny; m += kBlock) {
-        if (m < nx) twx_s[m] = twg[m];
-        else twy_s[m - nx] = twg[m];
-    }
-    __syncthreads();
+    const double2* twx = tw + R.tw_offset;            // e^{2 pi i m / nx}
+    const double2* twy = twx + nx;                    // e^{2 pi i m / ny}
     const T* src = fields + R.field_offset + (uint64_t)fld * R.n;
-    // y first: one column per thread, coalesced across lanes; n_y = 0..3
-    // (a real column has Y(-n_y) = conj(Y(n_y)))
-    const uint32_t cols = P * nx;                      // columns of this workgroup (all its planes)
-    for (uint32_t c = threadIdx.x; c < (P == 1 ? nx : cols); c += kBlock) {
-        const uint32_t p = c / nx, x = c % nx, z = z0 + p;
-        double y0 = 0.0, y1r = 0.0, y1i = 0.0, y2r = 0.0, y2i = 0.0, y3r = 0.0, y3i = 0.0;
-        if (z < nz) {
-            const T* col = src + (uint64_t)z * nx * ny + x;
-            uint32_t m2 = 0, m3 = 0;
-            for (uint32_t y = 0; y < ny; ++y) {
-                const double v = (double)col[(uint64_t)y * nx];
-                const double2 t1 = twy_s[y], t2 = twy_s[m2], t3 = twy_s[m3];
-                y0 += v;
-                y1r = fma(v, t1.x, y1r);
-                y1i = fma(-v, t1.y, y1i);
-                y2r = fma(v, t2.x, y2r);
-                y2i = fma(-v, t2.y, y2i);
-                y3r = fma(v, t3.x, y3r);
-                y3i = fma(-v, t3.y, y3i);
-                m2 += 2;
-                while (m2 >= ny) m2 -= ny;
-                m3 += 3;
-                while (m3 >= ny) m3 -= ny;
+    // Several planes per workgroup (nx <= kBlock / 2): one pass over all their
+    // columns.  One plane per workgroup: the columns come in passes of kBlock,
+    // and the 28 items (n_x, n_y) of the plane, owned by threads 0..27,
+    // accumulate over the passes in x order.  The LDS use does not depend on
+    // the box.
+    const uint32_t cols = P * nx;
+    const uint32_t pass_cols = P == 1 ? (uint32_t)kBlock : cols;
+    double acc_re = 0.0, acc_im = 0.0;
+    for (uint32_t c0 = 0; c0 < cols; c0 += pass_cols) {
+        // y first: one column per thread, coalesced across lanes; n_y = 0..3
+        // (a real column has Y(-n_y) = conj(Y(n_y))); the twiddle index is the
+        // same for every lane
+        const uint32_t c = c0 + threadIdx.x;
+        if (threadIdx.x < pass_cols && c < cols) {
+            const uint32_t p = c / nx, x = c % nx, z = z0 + p;
+            double y0 = 0.0, y1r = 0.0, y1i = 0.0, y2r = 0.0, y2i = 0.0, y3r = 0.0, y3i = 0.0;
+            if (z < nz) {
+                const T* col = src + (uint64_t)z * nx * ny + x;
+                uint32_t m2 = 0, m3 = 0;
+                for (uint32_t y = 0; y < ny; ++y) {
+                    const double v = (double)col[(uint64_t)y * nx];
+                    const double2 t1 = twy[y], t2 = twy[m2], t3 = twy[m3];
+                    y0 += v;
+                    y1r = fma(v, t1.x, y1r);
+                    y1i = fma(-v, t1.y, y1i);
+                    y2r = fma(v, t2.x, y2r);
+                    y2i = fma(-v, t2.y, y2i);
+                    y3r = fma(v, t3.x, y3r);
+                    y3i = fma(-v, t3.y, y3i);
+                    m2 += 2;
+                    while (m2 >= ny) m2 -= ny;
+                    m3 += 3;
+                    while (m3 >= ny) m3 -= ny;
+                }
             }
+            double2* Yc = Ys + (uint64_t)threadIdx.x * 4;
+            Yc[0] = make_double2(y0, 0.0);
+            Yc[1] = make_double2(y1r, y1i);
+            Yc[2] = make_double2(y2r, y2i);
+            Yc[3] = make_double2(y3r, y3i);
         }
-        double2* Yc = Ys + (uint64_t)c * 4;
-        Yc[0] = make_double2(y0, 0.0);
-        Yc[1] = make_double2(y1r, y1i);
-        Yc[2] = make_double2(y2r, y2i);
-        Yc[3] = make_double2(y3r, y3i);
-    }
-    __syncthreads();
-    // then x: item = (plane, n_x, n_y), a sum over the plane's columns
-    for (uint32_t it = threadIdx.x; it < P * kDftPlane; it += kBlock) {
-        const uint32_t p = it / kDftPlane, o = it % kDftPlane;
-        const uint32_t z = z0 + p;
-        if (z >= nz) continue;
-        const uint32_t q = o / kDftNy;
-        const int sy = (int)(o % kDftNy) - 3;
-        const uint32_t ay = (uint32_t)(sy < 0 ? -sy : sy);
-        const double sg = sy < 0 ? -1.0 : 1.0;          // conjugate for negative n_y
-        const double2* Yp = Ys + (uint64_t)p * nx * 4 + ay;
-        double re = 0.0, im = 0.0;
-        uint32_t m = 0;
-        for (uint32_t x = 0; x < nx; ++x) {
-            const double2 yv = Yp[(uint64_t)x * 4];
-            const double yr = yv.x, yi = sg * yv.y;
-            const double2 t = twx_s[m];
-            // (yr + i yi)(c - i s)
-            re += yr * t.x + yi * t.y;
-            im += yi * t.x - yr * t.y;
-            m += q;
-            while (m >= nx) m -= nx;
+        __syncthreads();
+        // then x over this pass's columns: item = (plane, n_x, n_y)
+        if (P > 1) {
+            // several planes, one pass: every item is finished here
+            for (uint32_t it = threadIdx.x; it < P * kDftPlane; it += kBlock) {
+                const uint32_t p = it / kDftPlane, o = it % kDftPlane;
+                const uint32_t z = z0 + p;
+                if (z >= nz) continue;
+                const double2 v = dft_x_item(Ys + (uint64_t)p * nx * 4, twx, nx, 0u, nx, o);
+                dft[R.dft_offset + ((uint64_t)fld * nz + z) * kDftPlane + o] = v;
+            }
+        } else if (threadIdx.x < kDftPlane) {
+            const double2 v = dft_x_item(Ys, twx, nx, c0, min(nx, c0 + (uint32_t)kBlock), threadIdx.x);
+            acc_re += v.x;
+            acc_im += v.y;
         }
-        dft[R.dft_offset + ((uint64_t)fld * nz + z) * kDftPlane + o] = make_double2(re, im);
+        __syncthreads();
     }
+    if (P == 1 && threadIdx.x < kDftPlane && z0 < nz)
+        dft[R.dft_offset + ((uint64_t)fld * nz + z0) * kDftPlane + threadIdx.x] = make_double2(acc_re, acc_im);
 }
 
 __device__ __forceinline__ int shell_of(int n2)
@@ -854,14 +878,13 @@ __global__ __launch_bounds__(kBlock) void dft_shell_kernel(const RepDev* reps, c
 }
 
 hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint32_t* chunks, uint32_t nchunks,
-                      const void* fields, const double2* tw, double2* dft, double2* zbuf, double* acc, size_t lds,
-                      hipStream_t s)
+                      const void* fields, const double2* tw, double2* dft, double2* zbuf, double* acc, hipStream_t s)
 {
     dim3 grid(nchunks, kFields);
     if (precision == kFP64)
-        dft_plane_kernel<double><<<grid, kBlock, lds, s>>>(reps, chunks, (const double*)fields, tw, dft);
+        dft_plane_kernel<double><<<grid, kBlock, 0, s>>>(reps, chunks, (const double*)fields, tw, dft);
     else
-        dft_plane_kernel<float><<<grid, kBlock, lds, s>>>(reps, chunks, (const float*)fields, tw, dft);
+        dft_plane_kernel<float><<<grid, kBlock, 0, s>>>(reps, chunks, (const float*)fields, tw, dft);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dft_z_kernel<<<dim3(nrep, kFields, kZSplit), kBlock, 0, s>>>(reps, tw, dft, zbuf);

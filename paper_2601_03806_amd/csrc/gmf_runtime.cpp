@@ -44,7 +44,6 @@ struct Layout {
     size_t reps = 0, blk2rep = 0, step = 0, acc = 0, tot = 0, mpart = 0;
     size_t fields = 0, partials = 0, dft = 0, chunks = 0, stage = 0, stage_bytes = 0, total = 0;
     uint32_t total_chunks = 0;     // workgroups of the first spectrum stage
-    size_t dft_lds = 0;
     size_t twiddles = 0, zbuf = 0;
     size_t sample_sq = 0;          // per-sample sums of squares (sampling)
     // full-box spectra (spectrum option)
@@ -124,7 +123,6 @@ int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         if (opt->spectrum != 0 && (opt->spectrum != 1 || opt->sample_every <= 0)) return GMF_EINVAL;
     }
     const size_t es = (opt && opt->precision == GMF_FP32_SHIFTED) ? 4 : 8;
-    const bool sampling = opt && opt->sample_every > 0;
     for (int r = 0; r < nrep; ++r) {
         const gmf_replica& R = reps[r];
         if (R.nx < 1 || R.ny < 1 || R.nz < 1 || R.reserved != 0) return GMF_EINVAL;
@@ -133,8 +131,6 @@ int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         if (n >= (1ull << 31) || (uint64_t)R.nx * R.ny * Q * es >= (1ull << 32)) return GMF_EINVAL;
         if (!finite_pos(R.rho0) || !std::isfinite(R.tau) || !(R.tau > 0.5)) return GMF_EINVAL;
         if (!std::isfinite(R.kbt) || R.kbt < 0.0) return GMF_EINVAL;
-        // the first spectrum stage keeps twiddles and y-transformed columns in LDS
-        if (sampling && dft_lds_bytes((uint32_t)R.nx, (uint32_t)R.ny) > 65536) return GMF_EINVAL;
         // full-box spectra: line lengths with prime factors 2, 3, 5 only, at most kFftMaxLen
         if (opt && opt->spectrum) {
             FftPlan pl;
@@ -161,7 +157,6 @@ Layout plan(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         {
             const uint32_t P = dft_planes_per_block((uint32_t)reps[r].nx);
             L.total_chunks += ((uint32_t)reps[r].nz + P - 1) / P;
-            L.dft_lds = std::max<size_t>(L.dft_lds, dft_lds_bytes((uint32_t)reps[r].nx, (uint32_t)reps[r].ny));
         }
         L.dft_complex += (uint32_t)(kFields * reps[r].nz * kDftPlane);
         L.tw_complex += (uint32_t)(reps[r].nx + reps[r].ny + reps[r].nz);
@@ -369,7 +364,7 @@ int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
                                ctx->stream));
         CK(launch_dft(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_chunks(), ctx->L.total_chunks,
                       ctx->d_fields(), ctx->d_twiddles(), reinterpret_cast<double2*>(ctx->d_dft()), ctx->d_zbuf(),
-                      ctx->d_acc(), ctx->L.dft_lds, ctx->stream));
+                      ctx->d_acc(), ctx->stream));
         if (ctx->L.spectrum)
             CK(launch_spectrum(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_sfirst(), ctx->L.spec_blocks,
                                ctx->d_fields(), ctx->d_twiddles(), ctx->d_spec(), ctx->d_sample_sq(),

@@ -213,13 +213,16 @@ def test_moments_and_conservation(w):
         assert np.max(np.abs(u - ou)) < 1e-13
 
 
-def test_sampled_statistics_match_oracle(w):
+@pytest.mark.parametrize("box", [(12, 10, 8), (600, 3, 2), (130, 5, 4)])
+def test_sampled_statistics_match_oracle(w, box):
     """The fused sampler (observables, spatial variances, shell spectra) equals
-    the oracle's brute-force observables of the same states."""
-    spec = gmf.ReplicaSpec(12, 10, 8, 1.0, 0.6, 1e-4, 5)
+    the oracle's brute-force observables of the same states; 600-wide rows take
+    the first DFT stage through three passes of columns, 130-wide rows one
+    plane per workgroup in one pass."""
+    spec = gmf.ReplicaSpec(*box, 1.0, 0.6, 1e-4, 5)
     p = oracle_params(spec)
     f = oracle.rest_state(p)
-    say("sampler vs oracle")
+    say(f"sampler vs oracle {box}")
     with gmf.Context([spec], precision=gmf.FP64, sample_every=25) as ctx:
         ctx.step(101)            # samples at t = 0, 25, 50, 75, 100
         st = ctx.stats()

@@ -123,9 +123,11 @@ def test_equilibrium_spectra_are_flat():
 
 
 @pytest.mark.parametrize("box,prec,rtol", [((96, 64, 80), gmf.FP32_SHIFTED, 1e-6), ((60, 72, 50), gmf.FP64, 1e-12),
+                                           ((1024, 6, 5), gmf.FP64, 1e-12), ((2, 3, 1024), gmf.FP64, 1e-12),
                                            ((256, 256, 256), gmf.FP32_SHIFTED, 1e-6)])
 def test_full_spectrum_large_boxes(box, prec, rtol):
-    """Mixed-radix lines (96 = 4 4 2 3, 80 = 4 4 5, 60, 72, 50) and the 256^3
+    """Mixed-radix lines (96 = 4 4 2 3, 80 = 4 4 5, 60, 72, 50), the longest
+    lines (1024 along x, and along z with two columns per tile), and the 256^3
     headline box, one sample of the equilibrating fluid 40 steps from rest,
     against the oracle's FFT of the same state."""
     spec = gmf.ReplicaSpec(*box, 1.0, 0.8, 1e-4, 1)
