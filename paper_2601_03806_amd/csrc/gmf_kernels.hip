@@ -697,22 +697,15 @@ __device__ __forceinline__ double2 dft_x_item(const double2* Yp, const double2* 
     return make_double2(re, im);
 }
 
+// One workgroup of the first stage.  twx / twy point either into LDS or into
+// the twiddle tables in memory; the caller branches once so that each path
+// keeps a single address space (no generic loads in the inner loops).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void dft_plane_kernel(const RepDev* reps, const uint32_t* chunks,
-                                                           const T* __restrict__ fields,
-                                                           const double2* __restrict__ tw, double2* dft)
+__device__ __forceinline__ void dft_plane_body(const RepDev& R, uint32_t z0, int fld, const T* __restrict__ fields,
+                                               const double2* twx, const double2* twy, double2* Ys, double2* dft)
 {
-    // Y[column][n_y = 0..3] of up to kBlock columns (one per thread)
-    __shared__ double2 Ys[kBlock * 4];
-    const uint32_t ck = chunks[blockIdx.x];
-    const int fld = blockIdx.y;
-    const int r = (int)(ck >> 16);
-    const RepDev R = uniform_rep(reps[r]);
     const uint32_t nx = R.nx, ny = R.ny, nz = R.nz;
     const uint32_t P = dft_planes_per_block(nx);
-    const uint32_t z0 = (ck & 0xffffu) * P;
-    const double2* twx = tw + R.tw_offset;            // e^{2 pi i m / nx}
-    const double2* twy = twx + nx;                    // e^{2 pi i m / ny}
     const T* src = fields + R.field_offset + (uint64_t)fld * R.n;
     // Several planes per workgroup (nx <= kBlock / 2): one pass over all their
     // columns.  One plane per workgroup: the columns come in passes of kBlock,
@@ -775,6 +768,31 @@ __global__ __launch_bounds__(kBlock) void dft_plane_kernel(const RepDev* reps, c
     }
     if (P == 1 && threadIdx.x < kDftPlane && z0 < nz)
         dft[R.dft_offset + ((uint64_t)fld * nz + z0) * kDftPlane + threadIdx.x] = make_double2(acc_re, acc_im);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dft_plane_kernel(const RepDev* reps, const uint32_t* chunks,
+                                                           const T* __restrict__ fields,
+                                                           const double2* __restrict__ tw, double2* dft)
+{
+    // Y[column][n_y = 0..3] of up to kBlock columns (one per thread), and the
+    // twiddles of both axes when they fit (else they are read from memory)
+    constexpr uint32_t kTwCache = 512;   // 8 KiB: with Ys, 24 KiB per workgroup (six per CU)
+    __shared__ double2 Ys[kBlock * 4];
+    __shared__ double2 tw_s[kTwCache];
+    const uint32_t ck = chunks[blockIdx.x];
+    const int fld = blockIdx.y;
+    const int r = (int)(ck >> 16);
+    const RepDev R = uniform_rep(reps[r]);
+    const uint32_t z0 = (ck & 0xffffu) * dft_planes_per_block(R.nx);
+    const double2* twg = tw + R.tw_offset;            // e^{2 pi i m / nx}, then e^{2 pi i m / ny}
+    if (R.nx + R.ny <= kTwCache) {
+        for (uint32_t m = threadIdx.x; m < R.nx + R.ny; m += kBlock) tw_s[m] = twg[m];
+        __syncthreads();
+        dft_plane_body<T>(R, z0, fld, fields, tw_s, tw_s + R.nx, Ys, dft);
+    } else {
+        dft_plane_body<T>(R, z0, fld, fields, twg, twg + R.nx, Ys, dft);
+    }
 }
 
 __device__ __forceinline__ int shell_of(int n2)
