@@ -124,15 +124,17 @@ __host__ __device__ inline uint64_t pop_base_offset(const RepDev& R, int p)
     const uint32_t s = (uint32_t)slot_of(p);
     return (uint64_t)(s / R.grp) * R.grp_elems + (uint64_t)(s % R.grp) * R.nx;
 }
-// Element offset of row (y, z) inside a group (valid for every population).
-__host__ __device__ inline uint32_t row_offset(const RepDev& R, uint32_t y, uint32_t z)
+// Element offset of row (y, z) inside a group (valid for every population),
+// in 32 bits: only for the per-node addressing modes, where a whole group
+// fits 32-bit byte offsets.
+__host__ __device__ inline uint32_t row_offset32(const RepDev& R, uint32_t y, uint32_t z)
 {
     return (z * R.ny + y) * R.row_stride;
 }
-// Full element offset of population p at node (x, y, z).
+// Full element offset of population p at node (x, y, z), any box.
 __host__ __device__ inline uint64_t pop_index(const RepDev& R, int p, uint32_t x, uint32_t y, uint32_t z)
 {
-    return pop_base_offset(R, p) + row_offset(R, y, z) + x;
+    return pop_base_offset(R, p) + (uint64_t)(z * R.ny + y) * R.row_stride + x;
 }
 
 // Streaming patterns of the step kernel.  Tensor order makes the opposite

@@ -166,11 +166,12 @@ __device__ __forceinline__ uint32_t slot_soff(const RepDev& R, int p)
     return (uint32_t)(slot_of(p) % G) * R.nx * (uint32_t)sizeof(T);
 }
 
+// Plain (cached) store of a sampled field value; 64-bit offsets, since a field
+// of a large FP64 box exceeds 4 GiB.
 template <typename T>
 __device__ __forceinline__ void stg_cached(T* base, uint32_t idx, T v)
 {
-    const uint32_t boff = idx * (uint32_t)sizeof(T);
-    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
+    base[(uint64_t)idx] = v;
 }
 
 // The replica record is read once per workgroup and pinned in scalar
@@ -304,7 +305,7 @@ __device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, 
     } else {
         // byte offsets: source row (y - cy, z - cz) at index 3*cyi + czi
 #pragma unroll
-        for (int q = 0; q < 9; ++q) rows[q] = row_offset(R, yv[q / 3], zv[q % 3]) * (uint32_t)sizeof(T);
+        for (int q = 0; q < 9; ++q) rows[q] = row_offset32(R, yv[q / 3], zv[q % 3]) * (uint32_t)sizeof(T);
         self = rows[4] + xb[1];
 #pragma unroll
         for (int p = 0; p < Q; ++p) {

@@ -212,3 +212,24 @@ def test_gmf_keeps_equilibrium_where_bgk_departs():
     assert np.min(g[1][1]) > 0.98 and np.min(b[1][1]) < 0.95                   # shells of the momentum spectrum
     for coll in (gmf.COLLISION_GMF, gmf.COLLISION_BGK):
         assert np.all(np.abs(res[(coll, 1.0)][0][idx] - 1) < 0.003)
+
+
+def test_largest_box_1024cube_aa_with_sampling(tabs):
+    """1024^3 (1.07e9 nodes, 58 GB of populations with the one-buffer AA
+    pattern), FP32 shifted, sampled every 2 steps: plane-uniform addressing is
+    the only one that fits; sampled nodes match the oracle's collision; mass and
+    momentum are conserved; the sampler's density variance is positive and
+    finite after the first steps from rest."""
+    spec = gmf.ReplicaSpec(1024, 1024, 1024, 1.0, 0.8, 1e-4, 3)
+    say("1024^3 AA FP32 with sampling")
+    with gmf.Context([spec], precision=gmf.FP32_SHIFTED, streaming=gmf.STREAM_AA, sample_every=2) as ctx:
+        cfg = ctx.config()
+        assert cfg["addressing"] == "plane" and cfg["streaming"] == "AA"
+        s0 = ctx.stats()
+        ctx.step(5)                                        # odd step count: the AA buffer is in its odd state
+        err = _sampled_collision_check(ctx, spec, 0, tabs, gmf.FP32_SHIFTED, 200, seed=4)
+        s1 = ctx.stats()
+    assert err < 2e-5, err
+    assert abs(s1["mass"] - s0["mass"]) < 1e-6 * s0["mass"]
+    assert np.all(np.abs(s1["momentum"]) < 1e-6 * s0["mass"])
+    assert s1["nsamples"] == 3 and np.isfinite(s1["sum_var"]).all() and s1["sum_var"][0] > 0
