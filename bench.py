@@ -38,7 +38,7 @@ def kernel_source_hash() -> str:
 
 def variant_key(cfg: dict) -> str:
     """Step-kernel variant as named in profiles/traffic.json."""
-    return f"{cfg['addressing']}/{cfg['streaming']}/npt{cfg['nodes_per_thread']}"
+    return f"{cfg['addressing']}/{cfg['streaming']}/npt{cfg['nodes_per_thread']}/{cfg['block_map']}"
 
 
 def measured_traffic(kernel_key: str, nodes: int, cfg: dict):

@@ -101,7 +101,7 @@ def lib() -> ctypes.CDLL:
         L.gmf_get_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         L.gmf_noise_probe.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32), dp]
-        L.gmf_get_config.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 5
+        L.gmf_get_config.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 6
         L.gmf_spectrum.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp, ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int32)]
         L.gmf_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, vp]
@@ -246,12 +246,13 @@ class Context:
         return v.value
 
     def config(self):
-        a, b, c, d, e = (ctypes.c_int32() for _ in range(5))
+        a, b, c, d, e, x = (ctypes.c_int32() for _ in range(6))
         _check(lib().gmf_get_config(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d),
-                                    ctypes.byref(e)), "gmf_get_config")
+                                    ctypes.byref(e), ctypes.byref(x)), "gmf_get_config")
         return {"nodes_per_thread": a.value, "block": b.value, "graph_steps": c.value,
                 "addressing": "plane" if d.value == 0 else f"group{d.value}",
-                "streaming": "AA" if e.value == STREAM_AA else "A/B"}
+                "streaming": "AA" if e.value == STREAM_AA else "A/B",
+                "block_map": f"xcd{x.value}" if x.value else "linear"}
 
     # data ------------------------------------------------------------------
     def moments(self, r: int = 0):

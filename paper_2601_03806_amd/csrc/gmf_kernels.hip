@@ -445,7 +445,16 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* out)
 template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int NPT, int G, int SM>
 __global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a)
 {
-    const uint32_t blk = blockIdx.x;
+    // Workgroups are dealt to the XCDs in turn (workgroup i to XCD i mod X).
+    // With a.xcd = X each XCD instead takes one contiguous range of lattice
+    // blocks, so the neighbouring rows that a block pulls from are mostly read
+    // through the same L2; the autotuner picks whichever is faster.
+    uint32_t blk = blockIdx.x;
+    if (a.xcd) {
+        const uint32_t per = (a.nblocks + a.xcd - 1u) / a.xcd;
+        blk = (blockIdx.x % a.xcd) * per + blockIdx.x / a.xcd;
+        if (blk >= a.nblocks) return;
+    }
     const int r = a.blk2rep ? (int)sgpr(a.blk2rep[blk]) : 0;
     const RepDev R = uniform_rep(a.reps[r]);
     const uint64_t t = sgpr64((uint64_t)(a.step_base + (a.d_step ? *a.d_step : 0)));
@@ -463,9 +472,12 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a)
 template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int G, int SM>
 static hipError_t launch_step_npt(int npt, const StepArgs& a, uint32_t nblocks, hipStream_t s)
 {
+    StepArgs b = a;
+    b.nblocks = nblocks;
+    const uint32_t g = a.xcd ? (nblocks + a.xcd - 1u) / a.xcd * a.xcd : nblocks;
     switch (npt) {
-    case 1: step_kernel<T, SHIFTED, COLL, SAMPLE, 1, G, SM><<<nblocks, kBlock, 0, s>>>(a); break;
-    case 2: step_kernel<T, SHIFTED, COLL, SAMPLE, 2, G, SM><<<nblocks, kBlock, 0, s>>>(a); break;
+    case 1: step_kernel<T, SHIFTED, COLL, SAMPLE, 1, G, SM><<<g, kBlock, 0, s>>>(b); break;
+    case 2: step_kernel<T, SHIFTED, COLL, SAMPLE, 2, G, SM><<<g, kBlock, 0, s>>>(b); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

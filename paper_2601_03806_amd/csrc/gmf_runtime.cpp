@@ -262,6 +262,8 @@ struct gmf_ctx {
     int grp = 27;                  // storage group size (see gmf_device.hpp)
     int mode = 0;                  // step-kernel addressing mode (choose_mode)
     bool aa = false;               // in-place AA streaming (else A/B)
+    uint32_t xcd_count = 1;        // XCDs of the device
+    bool xcd_map = false;          // each XCD takes a contiguous range of lattice blocks
     uint32_t nblocks = 0;          // lattice grid for the current npt
     int graph_steps = 0;           // 0: direct launches
     int period = 2;                // step pattern period (A/B parity, sampling)
@@ -354,6 +356,8 @@ int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
     a.step_base = in_graph ? (int64_t)j : t;
     a.fields = ctx->d_fields();
     a.partials = ctx->d_partials();
+    a.nblocks = ctx->nblocks;
+    a.xcd = ctx->xcd_map ? ctx->xcd_count : 0u;
     const bool sample = sampling_step(ctx, t);
     CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, step_pattern(ctx, t), ctx->mode, ctx->npt, a,
                    ctx->nblocks, ctx->stream));
@@ -453,9 +457,9 @@ int init_state(gmf_ctx* ctx)
     return GMF_OK;
 }
 
-// Time every fitting (streaming pattern, addressing mode, nodes per thread)
-// triple on the initial state, keep the fastest, and restore the initial state
-// in the chosen layout.  A/B re-runs the same step from the same source buffer;
+// Time every fitting (streaming pattern, addressing mode, nodes per thread,
+// workgroup-to-XCD mapping) combination on the initial state, keep the
+// fastest, and restore the initial state in the chosen layout.  A/B re-runs the same step from the same source buffer;
 // AA alternates its two step kinds in place (the state then changes, which
 // does not matter for the timing and is undone by the re-initialisation).
 // AA is a candidate only when the options leave the pattern open; A/B only
@@ -468,21 +472,26 @@ int autotune(gmf_ctx* ctx)
     std::vector<int> patterns;
     if (ctx->opt.streaming != GMF_STREAM_AA) patterns.push_back(GMF_STREAM_AB);
     if (ctx->opt.streaming != GMF_STREAM_AB) patterns.push_back(GMF_STREAM_AA);
-    std::string key = "v2p" + std::to_string(ctx->opt.precision) + "c" + std::to_string(ctx->opt.collision) + "s" +
+    std::string key = "v3p" + std::to_string(ctx->opt.precision) + "c" + std::to_string(ctx->opt.collision) + "s" +
                       std::to_string(ctx->opt.streaming);
     for (auto& r : ctx->reps) key += "_" + std::to_string(r.nx) + "x" + std::to_string(r.ny) + "x" + std::to_string(r.nz);
+    std::vector<int> maps = {0};
+    if (ctx->xcd_count > 1) maps.push_back(1);
     int best_mode = ctx->mode, best_npt = ctx->npt, best_pat = ctx->aa ? GMF_STREAM_AA : GMF_STREAM_AB;
+    int best_map = ctx->xcd_map ? 1 : 0;
     bool cached = false;
     if (cache) {
         if (FILE* fh = fopen(cache, "r")) {
             char k[4096];
-            int m, v, sp;
-            while (fscanf(fh, "%4095s %d %d %d", k, &m, &v, &sp) == 4)
+            int m, v, sp, xm;
+            while (fscanf(fh, "%4095s %d %d %d %d", k, &m, &v, &sp, &xm) == 5)
                 if (key == k && mode_fits(ctx->reps.data(), ctx->nrep, es, m, v) && (v == 1 || v == 2) &&
-                    std::find(patterns.begin(), patterns.end(), sp) != patterns.end()) {
+                    std::find(patterns.begin(), patterns.end(), sp) != patterns.end() &&
+                    std::find(maps.begin(), maps.end(), xm) != maps.end()) {
                     best_mode = m;
                     best_npt = v;
                     best_pat = sp;
+                    best_map = xm;
                     cached = true;
                 }
             fclose(fh);
@@ -497,6 +506,7 @@ int autotune(gmf_ctx* ctx)
         for (int pat : patterns) {
             for (int m : {27, 0, 3, 1}) {
                 for (int c : {1, 2}) {
+                  for (int xm : maps) {
                     if (!mode_fits(ctx->reps.data(), ctx->nrep, es, m, c)) continue;
                     set_layout(ctx, m);
                     int rc = build_grid(ctx, c);
@@ -511,6 +521,8 @@ int autotune(gmf_ctx* ctx)
                     a.step_base = ctx->step;
                     a.fields = nullptr;
                     a.partials = nullptr;
+                    a.nblocks = ctx->nblocks;
+                    a.xcd = xm ? ctx->xcd_count : 0u;
                     auto launch = [&](int i) {
                         const int sm = aa ? ((i & 1) ? kAALocal : kAAPull) : kAB;
                         return launch_step(ctx->opt.precision, ctx->opt.collision, false, sm, m, c, a, ctx->nblocks,
@@ -529,7 +541,9 @@ int autotune(gmf_ctx* ctx)
                         best_mode = m;
                         best_npt = c;
                         best_pat = pat;
+                        best_map = xm;
                     }
+                  }
                 }
             }
         }
@@ -537,12 +551,13 @@ int autotune(gmf_ctx* ctx)
         (void)hipEventDestroy(e1);
         if (cache) {
             if (FILE* fh = fopen(cache, "a")) {
-                fprintf(fh, "%s %d %d %d\n", key.c_str(), best_mode, best_npt, best_pat);
+                fprintf(fh, "%s %d %d %d %d\n", key.c_str(), best_mode, best_npt, best_pat, best_map);
                 fclose(fh);
             }
         }
     }
     ctx->aa = best_pat == GMF_STREAM_AA;
+    ctx->xcd_map = best_map == 1;
     set_layout(ctx, best_mode);
     int rc = build_grid(ctx, best_npt);
     if (rc != GMF_OK) return rc;
@@ -625,6 +640,15 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
     }
     ctx->grp = ctx->mode == 0 ? 27 : ctx->mode;
     ctx->aa = opt.streaming == GMF_STREAM_AA;
+    {
+        int nx = 0;
+        if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, ctx->device) == hipSuccess && nx > 1)
+            ctx->xcd_count = (uint32_t)nx;
+        else
+            (void)hipGetLastError();
+    }
+    // GMF_BLOCK_MAP = linear | xcd forces the workgroup-to-block mapping (tests)
+    if (const char* forced = getenv("GMF_BLOCK_MAP")) ctx->xcd_map = strcmp(forced, "xcd") == 0 && ctx->xcd_count > 1;
     // replica records
     uint64_t pop_off = 0, field_off = 0, spec_off = 0;
     uint32_t dft_off = 0, tw_off = 0, shell_off = 0;
@@ -947,9 +971,10 @@ int gmf_get_step(gmf_ctx* ctx, int64_t* t)
 }
 
 int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int32_t* graphs, int32_t* addressing,
-                   int32_t* streaming)
+                   int32_t* streaming, int32_t* xcd_map)
 {
     if (!ctx) return GMF_ESTATE;
+    if (xcd_map) *xcd_map = ctx->xcd_map ? (int32_t)ctx->xcd_count : 0;
     if (streaming) *streaming = ctx->aa ? GMF_STREAM_AA : GMF_STREAM_AB;
     if (nodes_per_thread) *nodes_per_thread = ctx->npt;
     if (block) *block = kBlock;
