@@ -215,8 +215,8 @@ int gmf_noise_probe(uint64_t seed, int64_t t, uint32_t node0, int32_t count, int
  * 27, 3, 1: per-node addressing with storage groups of that many populations),
  * the streaming pattern (GMF_STREAM_AB or GMF_STREAM_AA), and the workgroup
  * mapping (0: workgroup b updates lattice block b, so consecutive blocks go to
- * different XCDs; X > 0: each of the X XCDs updates one contiguous range of
- * blocks).  Any output pointer may be NULL. */
+ * different XCDs; C > 0: each XCD updates runs of C consecutive blocks of 256
+ * or 512 nodes).  Any output pointer may be NULL. */
 int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int32_t* graphs, int32_t* addressing,
                    int32_t* streaming, int32_t* xcd_map);
 

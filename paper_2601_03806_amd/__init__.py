@@ -252,7 +252,7 @@ class Context:
         return {"nodes_per_thread": a.value, "block": b.value, "graph_steps": c.value,
                 "addressing": "plane" if d.value == 0 else f"group{d.value}",
                 "streaming": "AA" if e.value == STREAM_AA else "A/B",
-                "block_map": f"xcd{x.value}" if x.value else "linear"}
+                "block_map": f"xcd/{x.value}" if x.value else "linear"}
 
     # data ------------------------------------------------------------------
     def moments(self, r: int = 0):

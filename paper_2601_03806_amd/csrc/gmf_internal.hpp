@@ -30,9 +30,10 @@ struct StepArgs {
     int64_t step_base;            // step = step_base + (d_step ? *d_step : 0)
     void* fields;                 // sampled fields (SAMPLE variants)
     double* partials;             // unused by the step kernel (kept for the sampling kernels)
-    uint32_t nblocks;             // workgroups of the lattice grid (set by launch_step)
-    uint32_t xcd;                 // 0: workgroup b takes lattice block b; else the number of XCDs
-                                  // and each XCD takes a contiguous range of blocks
+    uint32_t nblocks;             // lattice blocks (set by launch_step)
+    uint32_t xcd;                 // 0: workgroup b takes lattice block b; else the number of XCDs,
+                                  // each taking runs of `chunk` consecutive blocks
+    uint32_t chunk;               // blocks per run (0: one contiguous range per XCD)
 };
 
 // lattice kernels
@@ -40,7 +41,7 @@ struct StepArgs {
 // patterns need a.src == a.dst.
 // grp: addressing mode shared by every replica of the context: 0 (plane-uniform,
 // storage groups of 27) or the storage group size 27, 3 or 1 (per-node addressing)
-// a.xcd > 0: the grid is rounded up to a multiple of a.xcd (see step_kernel)
+// a.xcd > 0: the grid is rounded up to whole chunks on every XCD (see step_kernel)
 hipError_t launch_step(int precision, int collision, bool sample, int sm, int grp, int npt, const StepArgs& a,
                        uint32_t nblocks, hipStream_t s);
 hipError_t launch_init(int precision, void* buf, const RepDev* rep_dev, const RepDev& rep, hipStream_t s);

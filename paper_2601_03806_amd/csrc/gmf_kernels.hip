@@ -446,13 +446,15 @@ template <typename T, bool SHIFTED, int COLL, bool SAMPLE, int NPT, int G, int S
 __global__ __launch_bounds__(kBlock) void step_kernel(const StepArgs a)
 {
     // Workgroups are dealt to the XCDs in turn (workgroup i to XCD i mod X).
-    // With a.xcd = X each XCD instead takes one contiguous range of lattice
-    // blocks, so the neighbouring rows that a block pulls from are mostly read
-    // through the same L2; the autotuner picks whichever is faster.
+    // With a.xcd = X each XCD instead takes runs of a.chunk consecutive lattice
+    // blocks (chunk k of the lattice to XCD k mod X), so the neighbouring rows
+    // that a block pulls from are mostly read through the same L2; the
+    // autotuner picks the mapping.  The grid covers whole chunks on every XCD;
+    // the workgroups past the last block exit at once.
     uint32_t blk = blockIdx.x;
     if (a.xcd) {
-        const uint32_t per = (a.nblocks + a.xcd - 1u) / a.xcd;
-        blk = (blockIdx.x % a.xcd) * per + blockIdx.x / a.xcd;
+        const uint32_t x = blockIdx.x % a.xcd, j = blockIdx.x / a.xcd;
+        blk = (x + a.xcd * (j / a.chunk)) * a.chunk + j % a.chunk;
         if (blk >= a.nblocks) return;
     }
     const int r = a.blk2rep ? (int)sgpr(a.blk2rep[blk]) : 0;
@@ -474,7 +476,12 @@ static hipError_t launch_step_npt(int npt, const StepArgs& a, uint32_t nblocks, 
 {
     StepArgs b = a;
     b.nblocks = nblocks;
-    const uint32_t g = a.xcd ? (nblocks + a.xcd - 1u) / a.xcd * a.xcd : nblocks;
+    uint32_t g = nblocks;
+    if (a.xcd) {
+        // chunk 0: one contiguous range per XCD
+        b.chunk = a.chunk ? a.chunk : (nblocks + a.xcd - 1u) / a.xcd;
+        g = (nblocks + a.xcd * b.chunk - 1u) / (a.xcd * b.chunk) * b.chunk * a.xcd;
+    }
     switch (npt) {
     case 1: step_kernel<T, SHIFTED, COLL, SAMPLE, 1, G, SM><<<g, kBlock, 0, s>>>(b); break;
     case 2: step_kernel<T, SHIFTED, COLL, SAMPLE, 2, G, SM><<<g, kBlock, 0, s>>>(b); break;

@@ -30,6 +30,9 @@ constexpr size_t kAlign = 256;
 constexpr size_t kStageCap = 64ull << 20;   // staging for host transfers (per chunk of z planes)
 constexpr int kDefaultGraphSteps = 64;
 constexpr int kDefaultNpt = 1;
+// workgroup mappings: linear, one contiguous range per XCD, runs of 16 blocks per XCD
+constexpr int kXcdMaps = 3;
+constexpr uint32_t kXcdChunks[kXcdMaps] = {0u, 0u, 16u};
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -263,7 +266,7 @@ struct gmf_ctx {
     int mode = 0;                  // step-kernel addressing mode (choose_mode)
     bool aa = false;               // in-place AA streaming (else A/B)
     uint32_t xcd_count = 1;        // XCDs of the device
-    bool xcd_map = false;          // each XCD takes a contiguous range of lattice blocks
+    int xcd_map = 0;               // workgroup mapping: 0 linear, else an index into kXcdChunks
     uint32_t nblocks = 0;          // lattice grid for the current npt
     int graph_steps = 0;           // 0: direct launches
     int period = 2;                // step pattern period (A/B parity, sampling)
@@ -358,6 +361,7 @@ int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
     a.partials = ctx->d_partials();
     a.nblocks = ctx->nblocks;
     a.xcd = ctx->xcd_map ? ctx->xcd_count : 0u;
+    a.chunk = kXcdChunks[ctx->xcd_map];
     const bool sample = sampling_step(ctx, t);
     CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, step_pattern(ctx, t), ctx->mode, ctx->npt, a,
                    ctx->nblocks, ctx->stream));
@@ -476,9 +480,10 @@ int autotune(gmf_ctx* ctx)
                       std::to_string(ctx->opt.streaming);
     for (auto& r : ctx->reps) key += "_" + std::to_string(r.nx) + "x" + std::to_string(r.ny) + "x" + std::to_string(r.nz);
     std::vector<int> maps = {0};
-    if (ctx->xcd_count > 1) maps.push_back(1);
+    if (ctx->xcd_count > 1)
+        for (int xm = 1; xm < kXcdMaps; ++xm) maps.push_back(xm);
     int best_mode = ctx->mode, best_npt = ctx->npt, best_pat = ctx->aa ? GMF_STREAM_AA : GMF_STREAM_AB;
-    int best_map = ctx->xcd_map ? 1 : 0;
+    int best_map = ctx->xcd_map;
     bool cached = false;
     if (cache) {
         if (FILE* fh = fopen(cache, "r")) {
@@ -501,52 +506,62 @@ int autotune(gmf_ctx* ctx)
         hipEvent_t e0, e1;
         CK(hipEventCreate(&e0));
         CK(hipEventCreate(&e1));
-        float best_ms = 1e30f;
+        // every candidate is timed in two rounds (its faster one counts), so
+        // that a transient slowdown does not decide the choice
+        struct Cand {
+            int pat, m, c, xm;
+            float ms;
+        };
+        std::vector<Cand> cands;
+        for (int pat : patterns)
+            for (int m : {27, 0, 3, 1})
+                for (int c : {1, 2})
+                    for (int xm : maps)
+                        if (mode_fits(ctx->reps.data(), ctx->nrep, es, m, c)) cands.push_back({pat, m, c, xm, 1e30f});
         const int reps = 8;   // even: AA runs whole pull/local pairs
-        for (int pat : patterns) {
-            for (int m : {27, 0, 3, 1}) {
-                for (int c : {1, 2}) {
-                  for (int xm : maps) {
-                    if (!mode_fits(ctx->reps.data(), ctx->nrep, es, m, c)) continue;
-                    set_layout(ctx, m);
-                    int rc = build_grid(ctx, c);
-                    if (rc != GMF_OK) return rc;
-                    const bool aa = pat == GMF_STREAM_AA;
-                    StepArgs a;
-                    a.src = ctx->pop(0);
-                    a.dst = ctx->pop(aa ? 0 : 1);
-                    a.reps = ctx->d_reps();
-                    a.blk2rep = ctx->d_blk2rep();
-                    a.d_step = nullptr;
-                    a.step_base = ctx->step;
-                    a.fields = nullptr;
-                    a.partials = nullptr;
-                    a.nblocks = ctx->nblocks;
-                    a.xcd = xm ? ctx->xcd_count : 0u;
-                    auto launch = [&](int i) {
-                        const int sm = aa ? ((i & 1) ? kAALocal : kAAPull) : kAB;
-                        return launch_step(ctx->opt.precision, ctx->opt.collision, false, sm, m, c, a, ctx->nblocks,
-                                           ctx->stream);
-                    };
-                    CK(launch(0));
-                    CK(launch(1));
-                    CK(hipEventRecord(e0, ctx->stream));
-                    for (int i = 0; i < reps; ++i) CK(launch(i));
-                    CK(hipEventRecord(e1, ctx->stream));
-                    CK(hipEventSynchronize(e1));
-                    float ms = 0.f;
-                    CK(hipEventElapsedTime(&ms, e0, e1));
-                    if (ms < best_ms) {
-                        best_ms = ms;
-                        best_mode = m;
-                        best_npt = c;
-                        best_pat = pat;
-                        best_map = xm;
-                    }
-                  }
-                }
+        for (int round = 0; round < 2; ++round) {
+            for (Cand& cd : cands) {
+                set_layout(ctx, cd.m);
+                int rc = build_grid(ctx, cd.c);
+                if (rc != GMF_OK) return rc;
+                const bool aa = cd.pat == GMF_STREAM_AA;
+                StepArgs a;
+                a.src = ctx->pop(0);
+                a.dst = ctx->pop(aa ? 0 : 1);
+                a.reps = ctx->d_reps();
+                a.blk2rep = ctx->d_blk2rep();
+                a.d_step = nullptr;
+                a.step_base = ctx->step;
+                a.fields = nullptr;
+                a.partials = nullptr;
+                a.nblocks = ctx->nblocks;
+                a.xcd = cd.xm ? ctx->xcd_count : 0u;
+                a.chunk = kXcdChunks[cd.xm];
+                auto launch = [&](int i) {
+                    const int sm = aa ? ((i & 1) ? kAALocal : kAAPull) : kAB;
+                    return launch_step(ctx->opt.precision, ctx->opt.collision, false, sm, cd.m, cd.c, a, ctx->nblocks,
+                                       ctx->stream);
+                };
+                CK(launch(0));
+                CK(launch(1));
+                CK(hipEventRecord(e0, ctx->stream));
+                for (int i = 0; i < reps; ++i) CK(launch(i));
+                CK(hipEventRecord(e1, ctx->stream));
+                CK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                CK(hipEventElapsedTime(&ms, e0, e1));
+                cd.ms = std::min(cd.ms, ms);
             }
         }
+        float best_ms = 1e30f;
+        for (const Cand& cd : cands)
+            if (cd.ms < best_ms) {
+                best_ms = cd.ms;
+                best_mode = cd.m;
+                best_npt = cd.c;
+                best_pat = cd.pat;
+                best_map = cd.xm;
+            }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (cache) {
@@ -557,7 +572,7 @@ int autotune(gmf_ctx* ctx)
         }
     }
     ctx->aa = best_pat == GMF_STREAM_AA;
-    ctx->xcd_map = best_map == 1;
+    ctx->xcd_map = best_map;
     set_layout(ctx, best_mode);
     int rc = build_grid(ctx, best_npt);
     if (rc != GMF_OK) return rc;
@@ -647,8 +662,12 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         else
             (void)hipGetLastError();
     }
-    // GMF_BLOCK_MAP = linear | xcd forces the workgroup-to-block mapping (tests)
-    if (const char* forced = getenv("GMF_BLOCK_MAP")) ctx->xcd_map = strcmp(forced, "xcd") == 0 && ctx->xcd_count > 1;
+    // GMF_BLOCK_MAP = linear | xcd | xcd16 forces the workgroup-to-block mapping (tests)
+    if (const char* forced = getenv("GMF_BLOCK_MAP")) {
+        ctx->xcd_map = 0;
+        if (ctx->xcd_count > 1 && strcmp(forced, "xcd") == 0) ctx->xcd_map = 1;
+        if (ctx->xcd_count > 1 && strcmp(forced, "xcd16") == 0) ctx->xcd_map = 2;
+    }
     // replica records
     uint64_t pop_off = 0, field_off = 0, spec_off = 0;
     uint32_t dft_off = 0, tw_off = 0, shell_off = 0;
@@ -974,7 +993,11 @@ int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int3
                    int32_t* streaming, int32_t* xcd_map)
 {
     if (!ctx) return GMF_ESTATE;
-    if (xcd_map) *xcd_map = ctx->xcd_map ? (int32_t)ctx->xcd_count : 0;
+    if (xcd_map) {
+        // blocks each XCD takes at a time (0: linear mapping)
+        const uint32_t c = kXcdChunks[ctx->xcd_map];
+        *xcd_map = ctx->xcd_map == 0 ? 0 : (int32_t)(c ? c : (ctx->nblocks + ctx->xcd_count - 1) / ctx->xcd_count);
+    }
     if (streaming) *streaming = ctx->aa ? GMF_STREAM_AA : GMF_STREAM_AB;
     if (nodes_per_thread) *nodes_per_thread = ctx->npt;
     if (block) *block = kBlock;

@@ -136,19 +136,20 @@ def test_addressing_modes_bitwise(monkeypatch):
                 out[mode] = ctx.get_populations()
         monkeypatch.delenv("GMF_ADDRESSING")
         # workgroups mapped to contiguous block ranges per XCD
-        monkeypatch.setenv("GMF_BLOCK_MAP", "xcd")
-        for mode in ("plane", "27"):
-            monkeypatch.setenv("GMF_ADDRESSING", mode)
-            say(f"addressing mode={mode} xcd block map prec={prec}")
-            with gmf.Context([spec], precision=prec) as ctx:
-                ctx.step(12)
-                out["xcd" + mode] = ctx.get_populations()
+        for bmap in ("xcd", "xcd16"):
+            monkeypatch.setenv("GMF_BLOCK_MAP", bmap)
+            for mode in ("plane", "27"):
+                monkeypatch.setenv("GMF_ADDRESSING", mode)
+                say(f"addressing mode={mode} block map {bmap} prec={prec}")
+                with gmf.Context([spec], precision=prec) as ctx:
+                    ctx.step(12)
+                    out[bmap + mode] = ctx.get_populations()
         monkeypatch.delenv("GMF_ADDRESSING")
         monkeypatch.delenv("GMF_BLOCK_MAP")
         with gmf.Context([spec], precision=prec, tune=1) as ctx:
             ctx.step(12)
             out["tuned"] = ctx.get_populations()
-        for mode in ("plane", "27", "3", "1", "xcdplane", "xcd27", "tuned"):
+        for mode in ("plane", "27", "3", "1", "xcdplane", "xcd27", "xcd16plane", "xcd1627", "tuned"):
             assert np.array_equal(out[""], out[mode]), mode
 
 
