@@ -25,12 +25,13 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_NODE = {"fp32": 216, "fp64": 432}   # 27 loads + 27 stores per node update
+MOM_BYTES_PER_NODE = {"fp32": 80, "fp64": 160}  # moment storage: 10 loads + 10 stores per node update
 METRIC = "GLUPS & % HBM roofline, FP32-batched vs FP64-plain, at matched variance accuracy"
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("gmf_kernels.hip", "gmf_device.hpp", "gmf_math.hpp"):
+    for f in ("gmf_kernels.hip", "gmf_collide.hpp", "gmf_device.hpp", "gmf_math.hpp"):
         with open(os.path.join(ROOT, "paper_2601_03806_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -127,6 +128,15 @@ def run_gpu(args, torch, gmf, wl):
             sec = time_context(ctx, stream, ss, 10, torch)
             out["spectrum"] = {"seconds": sec, "nodes": spec.n, "steps": ss}
         torch.cuda.synchronize()
+        # the headline box in moment storage (ten moments per node), both precisions
+        for prec, key, st in ((gmf.FP32_SHIFTED, "mom_fp32", max(20, args.steps // 4)),
+                              (gmf.FP64, "mom_fp64", max(10, args.steps // 10))):
+            with gmf.Context([spec], precision=prec, stream=stream, tune=args.tune,
+                             storage=gmf.STORE_MOMENTS) as ctx:
+                print(f"[bench] {key} moment storage: steps {st}", file=sys.stderr, flush=True)
+                sec = time_context(ctx, stream, st, 4, torch)
+                out[key] = {"seconds": sec, "nodes": spec.n, "steps": st, "config": ctx.config()}
+            torch.cuda.synchronize()
         # 512^3 precision-stress box, both precisions
         wp = wl.precision_stress("fp32")
         bp = wp.boxes[0]
@@ -297,6 +307,16 @@ def main():
             gbs = BYTES_PER_NODE[bpn] * g
             line[key] = {"workload": name, "glups": round(g, 4), "gbs": round(gbs, 1),
                          "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "steps": r["steps"], "kernel_config": r["config"]}
+    for key, bpn in (("mom_fp32", "fp32"), ("mom_fp64", "fp64")):
+        if key in res:
+            r = res[key]
+            g = r["nodes"] * r["steps"] / r["seconds"] / 1e9
+            gbs = MOM_BYTES_PER_NODE[bpn] * g
+            line[f"{bpn}_moment_storage"] = {
+                "workload": f"d3q27_256cube_{bpn}_tau0.8, moment storage (ten moments per node)",
+                "glups": round(g, 4), "ms_per_step": round(r["seconds"] / r["steps"] * 1e3, 5),
+                "gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                "steps": r["steps"], "kernel_config": r["config"]}
     if not args.no_cpu and int(os.environ.get("RANK", 0)) == 0:
         print("[bench] oracle timing on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline()

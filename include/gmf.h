@@ -73,6 +73,22 @@ extern "C" {
                                neighbours and write back where they read, odd steps
                                read and write the node's own values): half the
                                population memory */
+/* gmf_options.storage: what the lattice keeps between steps. */
+#define GMF_STORE_POPULATIONS 0 /* the 27 populations of every node            */
+#define GMF_STORE_MOMENTS 1 /* the thread-safe formulation of Sec. II: the ten
+                               hydrodynamic moments of f(x, t) (Eqs. (3), (4),
+                               (13)), from which every node rebuilds the
+                               post-collision populations of its neighbours
+                               (their noise drawn again from the same Philox
+                               counters) and sums its new moments; 10 values
+                               read and written per node instead of 27.  GMF
+                               collision only (Eq. (10) keeps no ghost content,
+                               so the moments are the whole state that matters),
+                               two moment buffers (streaming AUTO or AB).  The
+                               populations that gmf_get_populations and
+                               gmf_get_nodes return are then the second-order
+                               Hermite populations of the stored moments, and
+                               gmf_set_populations keeps the moments of f. */
 
 /* observables accumulated by the sampler (index into gmf_stats_t arrays) */
 #define GMF_NOBS 10
@@ -123,6 +139,7 @@ typedef struct {
                              sampling step (needs sample_every > 0 and box lengths
                              whose prime factors are 2, 3, 5, at most 1024 each;
                              see gmf_spectrum); 0: off */
+    int32_t storage;      /* GMF_STORE_POPULATIONS or GMF_STORE_MOMENTS      */
 } gmf_options;
 
 typedef struct {
@@ -219,6 +236,11 @@ int gmf_noise_probe(uint64_t seed, int64_t t, uint32_t node0, int32_t count, int
  * or 512 nodes).  Any output pointer may be NULL. */
 int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int32_t* graphs, int32_t* addressing,
                    int32_t* streaming, int32_t* xcd_map);
+/* Storage kind in use (GMF_STORE_*) and, for moment storage, the tile of one
+ * workgroup of the step kernel: tile_x x tile_y nodes (plus a one-node halo)
+ * marched over tile_z z planes (0, 0, 0 for population storage).  Any output
+ * pointer may be NULL. */
+int gmf_get_tiling(gmf_ctx* ctx, int32_t* storage, int32_t* tile_x, int32_t* tile_y, int32_t* tile_z);
 
 /* Bandwidth reference: enqueue one plain streaming copy of `bytes` (a positive
  * multiple of 16) from device buffer src to device buffer dst (both 16-byte

@@ -29,6 +29,8 @@ COLLISION_BGK = 1
 STREAM_AUTO = 0
 STREAM_AB = 1
 STREAM_AA = 2
+STORE_POPULATIONS = 0
+STORE_MOMENTS = 1
 
 NOBS = 10
 NSPEC = 5
@@ -40,7 +42,7 @@ Q = 27
 EXPORTED = (
     "gmf_workspace_bytes", "gmf_init", "gmf_step", "gmf_moments", "gmf_stats", "gmf_reset_stats",
     "gmf_get_populations", "gmf_set_populations", "gmf_get_nodes", "gmf_get_step", "gmf_noise_probe",
-    "gmf_get_config", "gmf_copy_probe", "gmf_destroy", "gmf_strerror", "gmf_spectrum",
+    "gmf_get_config", "gmf_copy_probe", "gmf_destroy", "gmf_strerror", "gmf_spectrum", "gmf_get_tiling",
 )
 
 
@@ -53,7 +55,7 @@ class Replica(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("collision", ctypes.c_int32), ("noise_rho", ctypes.c_int32),
                 ("sample_every", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("tune", ctypes.c_int32),
-                ("streaming", ctypes.c_int32), ("spectrum", ctypes.c_int32)]
+                ("streaming", ctypes.c_int32), ("spectrum", ctypes.c_int32), ("storage", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -102,6 +104,7 @@ def lib() -> ctypes.CDLL:
         L.gmf_noise_probe.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32), dp]
         L.gmf_get_config.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 6
+        L.gmf_get_tiling.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 4
         L.gmf_spectrum.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp, ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int32)]
         L.gmf_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, vp]
@@ -112,7 +115,7 @@ def lib() -> ctypes.CDLL:
         L.gmf_strerror.restype = ctypes.c_char_p
         for name in ("gmf_init", "gmf_step", "gmf_moments", "gmf_stats", "gmf_reset_stats",
                      "gmf_get_populations", "gmf_set_populations", "gmf_get_nodes", "gmf_get_step",
-                     "gmf_noise_probe", "gmf_get_config", "gmf_spectrum"):
+                     "gmf_noise_probe", "gmf_get_config", "gmf_spectrum", "gmf_get_tiling"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -155,11 +158,11 @@ def make_replicas(specs):
 
 
 def make_options(precision=FP64, collision=COLLISION_GMF, noise_rho=0, sample_every=0, graph_steps=-1, tune=0,
-                 streaming=STREAM_AUTO, spectrum=0):
+                 streaming=STREAM_AUTO, spectrum=0, storage=STORE_POPULATIONS):
     o = Options()
     o.precision, o.collision, o.noise_rho = precision, collision, noise_rho
     o.sample_every, o.graph_steps, o.tune = sample_every, graph_steps, tune
-    o.streaming, o.spectrum = streaming, spectrum
+    o.streaming, o.spectrum, o.storage = streaming, spectrum, storage
     return o
 
 
@@ -193,11 +196,12 @@ class Context:
     """
 
     def __init__(self, specs, *, precision=FP64, collision=COLLISION_GMF, noise_rho=0, sample_every=0,
-                 graph_steps=-1, tune=0, streaming=STREAM_AUTO, spectrum=0, workspace="torch", stream=None):
+                 graph_steps=-1, tune=0, streaming=STREAM_AUTO, spectrum=0, storage=STORE_POPULATIONS,
+                 workspace="torch", stream=None):
         self.specs = list(specs)
         self._reps = make_replicas(self.specs)
         self._opt = make_options(precision, collision, noise_rho, sample_every, graph_steps, tune, streaming,
-                                 spectrum)
+                                 spectrum, storage)
         self.precision = precision
         self._ws = None
         ws_ptr, ws_bytes = None, 0
@@ -249,10 +253,17 @@ class Context:
         a, b, c, d, e, x = (ctypes.c_int32() for _ in range(6))
         _check(lib().gmf_get_config(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d),
                                     ctypes.byref(e), ctypes.byref(x)), "gmf_get_config")
-        return {"nodes_per_thread": a.value, "block": b.value, "graph_steps": c.value,
-                "addressing": "plane" if d.value == 0 else f"group{d.value}",
-                "streaming": "AA" if e.value == STREAM_AA else "A/B",
-                "block_map": f"xcd/{x.value}" if x.value else "linear"}
+        st, tx, ty, tz = (ctypes.c_int32() for _ in range(4))
+        _check(lib().gmf_get_tiling(self._h, ctypes.byref(st), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(tz)),
+               "gmf_get_tiling")
+        cfg = {"nodes_per_thread": a.value, "block": b.value, "graph_steps": c.value,
+               "addressing": "plane" if d.value == 0 else ("none" if d.value < 0 else f"group{d.value}"),
+               "streaming": "AA" if e.value == STREAM_AA else "A/B",
+               "block_map": f"xcd/{x.value}" if x.value else "linear",
+               "storage": "moments" if st.value == STORE_MOMENTS else "populations"}
+        if st.value == STORE_MOMENTS:
+            cfg["tile"] = f"{tx.value}x{ty.value}x{tz.value}"
+        return cfg
 
     # data ------------------------------------------------------------------
     def moments(self, r: int = 0):

@@ -34,7 +34,21 @@ struct StepArgs {
     uint32_t xcd;                 // 0: workgroup b takes lattice block b; else the number of XCDs,
                                   // each taking runs of `chunk` consecutive blocks
     uint32_t chunk;               // blocks per run (0: one contiguous range per XCD)
+    uint32_t tz;                  // moment storage: z planes per tile
 };
+
+// Moment storage (gmf_mstep.hip): the state is kMom fields of N values per
+// replica, the raw moments of g = f - w rho0 of the pre-collision state:
+//   0: rho - rho0, 1-3: j_x, j_y, j_z, 4-6: Pi_aa - rho0 cs2 (a = x, y, z),
+//   7: Pi_xy, 8: Pi_xz, 9: Pi_yz.
+constexpr int kMom = 10;
+// tile shapes (x, y) of the moment-storage step kernel; a workgroup has one
+// thread per column of the tile plus its one-node halo, rounded up to whole
+// wavefronts
+constexpr int kMTiles = 3;
+constexpr int kMTileX[kMTiles] = {64, 32, 32};
+constexpr int kMTileY[kMTiles] = {8, 16, 8};
+constexpr int mtile_threads(int t) { return ((kMTileX[t] + 2) * (kMTileY[t] + 2) + 63) / 64 * 64; }
 
 // lattice kernels
 // sm: streaming pattern kAB, kAAPull or kAALocal (gmf_device.hpp); the AA
@@ -81,6 +95,21 @@ hipError_t launch_nodes(int precision, const void* src, const RepDev* rep_dev, c
                         int32_t count, double* out, int aa_odd, hipStream_t s);
 hipError_t launch_noise_probe(int precision, uint64_t seed, int64_t t, uint32_t node0, int32_t count,
                               uint32_t* words, double* normals, hipStream_t s);
+
+// moment storage: one step (tile: index into kMTileX/Y; a.tz planes per tile;
+// nblocks tiles in all, RepDev::block_begin/nblocks per replica), the rest state
+// (zeros), and the host-interface helpers in the same conventions as the
+// population ones above (populations are the second-order Hermite
+// populations of the stored moments)
+hipError_t launch_mstep(int precision, bool sample, int tile, const StepArgs& a, uint32_t nblocks, hipStream_t s);
+hipError_t launch_mgather(int precision, const void* src, const RepDev* rep_dev, const RepDev& rep,
+                          uint32_t z0, uint32_t z1, double* out, hipStream_t s);
+hipError_t launch_mscatter(int precision, void* dst, const RepDev* rep_dev, const RepDev& rep,
+                           uint32_t z0, uint32_t z1, const double* in, hipStream_t s);
+hipError_t launch_mmoments(int precision, const void* src, const RepDev* rep_dev, const RepDev& rep,
+                           uint32_t z0, uint32_t z1, double* rho, double* u, double* partials, hipStream_t s);
+hipError_t launch_mnodes(int precision, const void* src, const RepDev* rep_dev, const int64_t* nodes,
+                         int32_t count, double* out, hipStream_t s);
 
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 

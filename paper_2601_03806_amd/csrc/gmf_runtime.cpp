@@ -33,6 +33,11 @@ constexpr int kDefaultNpt = 1;
 // workgroup mappings: linear, one contiguous range per XCD, runs of 16 blocks per XCD
 constexpr int kXcdMaps = 3;
 constexpr uint32_t kXcdChunks[kXcdMaps] = {0u, 0u, 16u};
+// moment storage: z planes per tile tried by the autotuner, and the default tile
+constexpr int kMTzCount = 4;
+constexpr uint32_t kMTz[kMTzCount] = {8u, 16u, 32u, 64u};
+constexpr int kDefaultMTile = 0;
+constexpr uint32_t kDefaultMTz = 32u;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -124,6 +129,10 @@ int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         if (opt->sample_every < 0 || opt->tune < 0 || opt->tune > 1) return GMF_EINVAL;
         if (opt->streaming < GMF_STREAM_AUTO || opt->streaming > GMF_STREAM_AA) return GMF_EINVAL;
         if (opt->spectrum != 0 && (opt->spectrum != 1 || opt->sample_every <= 0)) return GMF_EINVAL;
+        if (opt->storage != GMF_STORE_POPULATIONS && opt->storage != GMF_STORE_MOMENTS) return GMF_EINVAL;
+        if (opt->storage == GMF_STORE_MOMENTS &&
+            (opt->collision != GMF_COLLISION_GMF || opt->streaming == GMF_STREAM_AA))
+            return GMF_EINVAL;
     }
     const size_t es = (opt && opt->precision == GMF_FP32_SHIFTED) ? 4 : 8;
     for (int r = 0; r < nrep; ++r) {
@@ -181,7 +190,20 @@ Layout plan(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         off = align_up(off + std::max<size_t>(bytes, 1));
         return o;
     };
-    L.pop_bytes = (size_t)L.total_nodes * Q * es;
+    const bool mom = opt && opt->storage == GMF_STORE_MOMENTS;
+    if (mom) {
+        // tiles of the moment-storage step at the shortest tile depth, for the block table
+        uint64_t most = 0;
+        for (int t = 0; t < kMTiles; ++t) {
+            uint64_t tiles = 0;
+            for (int r = 0; r < nrep; ++r)
+                tiles += (uint64_t)((reps[r].nx + kMTileX[t] - 1) / kMTileX[t]) *
+                         ((reps[r].ny + kMTileY[t] - 1) / kMTileY[t]) * ((reps[r].nz + kMTz[0] - 1) / kMTz[0]);
+            most = std::max(most, tiles);
+        }
+        L.max_blocks = (uint32_t)std::max<uint64_t>(L.max_blocks, most);
+    }
+    L.pop_bytes = (size_t)L.total_nodes * (mom ? kMom : Q) * es;
     L.popA = take(L.pop_bytes);
     L.popB = (opt && opt->streaming == GMF_STREAM_AA) ? L.popA : take(L.pop_bytes);
     L.reps = take(sizeof(RepDev) * nrep);
@@ -231,6 +253,7 @@ gmf_options default_options()
     o.precision = GMF_FP64;
     o.collision = GMF_COLLISION_GMF;
     o.graph_steps = -1;
+    o.storage = GMF_STORE_POPULATIONS;
     return o;
 }
 
@@ -265,6 +288,9 @@ struct gmf_ctx {
     int grp = 27;                  // storage group size (see gmf_device.hpp)
     int mode = 0;                  // step-kernel addressing mode (choose_mode)
     bool aa = false;               // in-place AA streaming (else A/B)
+    bool mom = false;              // moment storage (gmf_mstep.hip); the two buffers alternate like A/B
+    int mtile = kDefaultMTile;     // moment storage: tile shape (index into kMTileX/Y)
+    uint32_t mtz = kDefaultMTz;    // moment storage: z planes per tile
     uint32_t xcd_count = 1;        // XCDs of the device
     int xcd_map = 0;               // workgroup mapping: 0 linear, else an index into kXcdChunks
     uint32_t nblocks = 0;          // lattice grid for the current npt
@@ -321,7 +347,11 @@ int build_grid(gmf_ctx* ctx, int npt)
         RepDev& R = ctx->rdev[r];
         const uint32_t per = (uint32_t)kBlock * (uint32_t)npt;
         R.block_begin = b;
-        R.nblocks = (R.n + per - 1) / per;
+        if (ctx->mom)
+            R.nblocks = ((R.nx + kMTileX[ctx->mtile] - 1) / kMTileX[ctx->mtile]) *
+                        ((R.ny + kMTileY[ctx->mtile] - 1) / kMTileY[ctx->mtile]) * ((R.nz + ctx->mtz - 1) / ctx->mtz);
+        else
+            R.nblocks = (R.n + per - 1) / per;
         b += R.nblocks;
         if (ctx->nrep > 1) map.insert(map.end(), R.nblocks, (uint16_t)r);
     }
@@ -362,9 +392,13 @@ int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
     a.nblocks = ctx->nblocks;
     a.xcd = ctx->xcd_map ? ctx->xcd_count : 0u;
     a.chunk = kXcdChunks[ctx->xcd_map];
+    a.tz = ctx->mtz;
     const bool sample = sampling_step(ctx, t);
-    CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, step_pattern(ctx, t), ctx->mode, ctx->npt, a,
-                   ctx->nblocks, ctx->stream));
+    if (ctx->mom)
+        CK(launch_mstep(ctx->opt.precision, sample, ctx->mtile, a, ctx->nblocks, ctx->stream));
+    else
+        CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, step_pattern(ctx, t), ctx->mode, ctx->npt, a,
+                       ctx->nblocks, ctx->stream));
     if (sample) {
         CK(launch_observables(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_fields(), ctx->d_partials(),
                               ctx->stream));
@@ -454,6 +488,12 @@ void set_layout(gmf_ctx* ctx, int m)
 // Rest equilibrium in the buffer that the next step reads.
 int init_state(gmf_ctx* ctx)
 {
+    // moment storage: the rest state has zero shifted moments
+    if (ctx->mom) {
+        CK(hipMemsetAsync(ctx->cur_pop(), 0, ctx->L.pop_bytes, ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+        return GMF_OK;
+    }
     for (int r = 0; r < ctx->nrep; ++r)
         CK(launch_init(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, ctx->rdev[r],
                        ctx->stream));
@@ -537,6 +577,7 @@ int autotune(gmf_ctx* ctx)
                 a.nblocks = ctx->nblocks;
                 a.xcd = cd.xm ? ctx->xcd_count : 0u;
                 a.chunk = kXcdChunks[cd.xm];
+                a.tz = 0;
                 auto launch = [&](int i) {
                     const int sm = aa ? ((i & 1) ? kAALocal : kAAPull) : kAB;
                     return launch_step(ctx->opt.precision, ctx->opt.collision, false, sm, cd.m, cd.c, a, ctx->nblocks,
@@ -575,6 +616,105 @@ int autotune(gmf_ctx* ctx)
     ctx->xcd_map = best_map;
     set_layout(ctx, best_mode);
     int rc = build_grid(ctx, best_npt);
+    if (rc != GMF_OK) return rc;
+    return init_state(ctx);
+}
+
+// Moment storage: time every (tile shape, tile depth, workgroup mapping) on
+// the initial state like autotune() does for populations, keep the fastest,
+// and restore the initial state.  Cache entries share the file and its line
+// format (key and four integers).
+int autotune_moments(gmf_ctx* ctx)
+{
+    const char* cache = getenv("GMF_TUNE_CACHE");
+    std::string key = "m1p" + std::to_string(ctx->opt.precision);
+    for (auto& r : ctx->reps) key += "_" + std::to_string(r.nx) + "x" + std::to_string(r.ny) + "x" + std::to_string(r.nz);
+    std::vector<int> maps = {0};
+    if (ctx->xcd_count > 1)
+        for (int xm = 1; xm < kXcdMaps; ++xm) maps.push_back(xm);
+    int best_tile = ctx->mtile, best_map = ctx->xcd_map;
+    uint32_t best_tz = ctx->mtz;
+    bool cached = false;
+    if (cache) {
+        if (FILE* fh = fopen(cache, "r")) {
+            char k[4096];
+            int tl, tz, xm, unused;
+            while (fscanf(fh, "%4095s %d %d %d %d", k, &tl, &tz, &xm, &unused) == 5)
+                if (key == k && tl >= 0 && tl < kMTiles && tz >= 1 &&
+                    std::find(maps.begin(), maps.end(), xm) != maps.end()) {
+                    best_tile = tl;
+                    best_tz = (uint32_t)tz;
+                    best_map = xm;
+                    cached = true;
+                }
+            fclose(fh);
+        }
+    }
+    if (!cached) {
+        hipEvent_t e0, e1;
+        CK(hipEventCreate(&e0));
+        CK(hipEventCreate(&e1));
+        struct Cand {
+            int tile;
+            uint32_t tz;
+            int xm;
+            float ms;
+        };
+        std::vector<Cand> cands;
+        for (int tl = 0; tl < kMTiles; ++tl)
+            for (uint32_t tz : kMTz)
+                for (int xm : maps) cands.push_back({tl, tz, xm, 1e30f});
+        const int reps = 8;
+        for (int round = 0; round < 2; ++round) {
+            for (Cand& cd : cands) {
+                ctx->mtile = cd.tile;
+                ctx->mtz = cd.tz;
+                int rc = build_grid(ctx, 1);
+                if (rc != GMF_OK) return rc;
+                StepArgs a;
+                std::memset(&a, 0, sizeof(a));
+                a.src = ctx->pop(0);
+                a.dst = ctx->pop(1);
+                a.reps = ctx->d_reps();
+                a.blk2rep = ctx->d_blk2rep();
+                a.step_base = ctx->step;
+                a.nblocks = ctx->nblocks;
+                a.xcd = cd.xm ? ctx->xcd_count : 0u;
+                a.chunk = kXcdChunks[cd.xm];
+                a.tz = cd.tz;
+                auto launch = [&]() { return launch_mstep(ctx->opt.precision, false, cd.tile, a, ctx->nblocks, ctx->stream); };
+                CK(launch());
+                CK(launch());
+                CK(hipEventRecord(e0, ctx->stream));
+                for (int i = 0; i < reps; ++i) CK(launch());
+                CK(hipEventRecord(e1, ctx->stream));
+                CK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                CK(hipEventElapsedTime(&ms, e0, e1));
+                cd.ms = std::min(cd.ms, ms);
+            }
+        }
+        float best_ms = 1e30f;
+        for (const Cand& cd : cands)
+            if (cd.ms < best_ms) {
+                best_ms = cd.ms;
+                best_tile = cd.tile;
+                best_tz = cd.tz;
+                best_map = cd.xm;
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (cache) {
+            if (FILE* fh = fopen(cache, "a")) {
+                fprintf(fh, "%s %d %u %d 0\n", key.c_str(), best_tile, best_tz, best_map);
+                fclose(fh);
+            }
+        }
+    }
+    ctx->mtile = best_tile;
+    ctx->mtz = best_tz;
+    ctx->xcd_map = best_map;
+    int rc = build_grid(ctx, 1);
     if (rc != GMF_OK) return rc;
     return init_state(ctx);
 }
@@ -655,6 +795,15 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
     }
     ctx->grp = ctx->mode == 0 ? 27 : ctx->mode;
     ctx->aa = opt.streaming == GMF_STREAM_AA;
+    ctx->mom = opt.storage == GMF_STORE_MOMENTS;
+    // GMF_MTILE = "tile,depth" forces the moment-storage tile (tests)
+    if (const char* forced = getenv("GMF_MTILE")) {
+        int tl = -1, tz = 0;
+        if (sscanf(forced, "%d,%d", &tl, &tz) == 2 && tl >= 0 && tl < kMTiles && tz >= (int)kMTz[0]) {
+            ctx->mtile = tl;
+            ctx->mtz = (uint32_t)tz;
+        }
+    }
     {
         int nx = 0;
         if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, ctx->device) == hipSuccess && nx > 1)
@@ -691,7 +840,7 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         // observables reduction: at least 16 nodes per thread, at most kObsChunks workgroups
         R.obs_chunks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kObsChunks, R.n / (16u * kBlock)));
         tw_off += R.nx + R.ny + R.nz;
-        pop_off += (uint64_t)Q * R.n;
+        pop_off += (uint64_t)(ctx->mom ? kMom : Q) * R.n;
         field_off += (uint64_t)kFields * R.n;
         dft_off += (uint32_t)(kFields * R.nz * kDftPlane);
         R.key0 = (uint32_t)in.seed;
@@ -780,7 +929,7 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         return GMF_EDEVICE;
     }
     if (opt.tune) {
-        rc = autotune(ctx);
+        rc = ctx->mom ? autotune_moments(ctx) : autotune(ctx);
         if (rc != GMF_OK) {
             gmf_destroy(ctx);
             return rc;
@@ -813,8 +962,12 @@ int gmf_moments(gmf_ctx* ctx, int32_t r, double* rho, double* u)
         const uint32_t z1 = std::min(R.nz, z0 + cp);
         const uint64_t cnt = plane * (z1 - z0);
         double* su = srho + cnt;
-        CK(launch_moments(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, srho, su,
-                          ctx->d_mpart(), ctx->aa_odd(), ctx->stream));
+        if (ctx->mom)
+            CK(launch_mmoments(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, srho, su,
+                               ctx->d_mpart(), ctx->stream));
+        else
+            CK(launch_moments(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, srho, su,
+                              ctx->d_mpart(), ctx->aa_odd(), ctx->stream));
         CK(hipStreamSynchronize(ctx->stream));
         if (rho) CK(hipMemcpy(rho + plane * z0, srho, sizeof(double) * cnt, hipMemcpyDeviceToHost));
         if (u)
@@ -839,8 +992,12 @@ int gmf_stats(gmf_ctx* ctx, int32_t r, gmf_stats_t* out)
         const uint32_t z1 = std::min(R.nz, z0 + cp);
         const uint64_t cnt = plane * (z1 - z0);
         const uint32_t nb = (uint32_t)((cnt + kBlock - 1) / kBlock);
-        CK(launch_moments(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, nullptr, nullptr,
-                          ctx->d_mpart(), ctx->aa_odd(), ctx->stream));
+        if (ctx->mom)
+            CK(launch_mmoments(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, nullptr, nullptr,
+                               ctx->d_mpart(), ctx->stream));
+        else
+            CK(launch_moments(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, nullptr, nullptr,
+                              ctx->d_mpart(), ctx->aa_odd(), ctx->stream));
         CK(launch_sum_partials(ctx->d_mpart(), nb, ctx->d_tot(), first ? 0 : 1, ctx->stream));
         first = false;
     }
@@ -920,8 +1077,11 @@ int gmf_get_populations(gmf_ctx* ctx, int32_t r, double* f)
     for (uint32_t z0 = 0; z0 < R.nz; z0 += cp) {
         const uint32_t z1 = std::min(R.nz, z0 + cp);
         const uint64_t cnt = plane * (z1 - z0);
-        CK(launch_gather(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, st, ctx->aa_odd(),
-                         ctx->stream));
+        if (ctx->mom)
+            CK(launch_mgather(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, st, ctx->stream));
+        else
+            CK(launch_gather(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, st, ctx->aa_odd(),
+                             ctx->stream));
         CK(hipStreamSynchronize(ctx->stream));
         for (int i = 0; i < Q; ++i)
             CK(hipMemcpy(f + (uint64_t)i * R.n + plane * z0, st + (uint64_t)i * cnt, sizeof(double) * cnt,
@@ -947,8 +1107,11 @@ int gmf_set_populations(gmf_ctx* ctx, int32_t r, const double* f)
         for (int i = 0; i < Q; ++i)
             CK(hipMemcpy(st + (uint64_t)i * cnt, f + (uint64_t)i * R.n + plane * z0, sizeof(double) * cnt,
                          hipMemcpyHostToDevice));
-        CK(launch_scatter(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, st, ctx->aa_odd(),
-                          ctx->stream));
+        if (ctx->mom)
+            CK(launch_mscatter(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, st, ctx->stream));
+        else
+            CK(launch_scatter(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, st, ctx->aa_odd(),
+                              ctx->stream));
         CK(hipStreamSynchronize(ctx->stream));
     }
     return GMF_OK;
@@ -973,8 +1136,11 @@ int gmf_get_nodes(gmf_ctx* ctx, int32_t r, const int64_t* nodes, int32_t count, 
         double* dout = reinterpret_cast<double*>(st + align_up(sizeof(int64_t) * (size_t)c));
         CK(hipStreamSynchronize(ctx->stream));
         CK(hipMemcpy(dn, nodes + j0, sizeof(int64_t) * c, hipMemcpyHostToDevice));
-        CK(launch_nodes(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, dn, c, dout, ctx->aa_odd(),
-                        ctx->stream));
+        if (ctx->mom)
+            CK(launch_mnodes(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, dn, c, dout, ctx->stream));
+        else
+            CK(launch_nodes(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, dn, c, dout, ctx->aa_odd(),
+                            ctx->stream));
         CK(hipStreamSynchronize(ctx->stream));
         CK(hipMemcpy(f + (size_t)j0 * Q, dout, sizeof(double) * Q * c, hipMemcpyDeviceToHost));
     }
@@ -1000,9 +1166,19 @@ int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int3
     }
     if (streaming) *streaming = ctx->aa ? GMF_STREAM_AA : GMF_STREAM_AB;
     if (nodes_per_thread) *nodes_per_thread = ctx->npt;
-    if (block) *block = kBlock;
+    if (block) *block = ctx->mom ? mtile_threads(ctx->mtile) : kBlock;
     if (graphs) *graphs = ctx->graph_steps;
-    if (addressing) *addressing = ctx->mode;
+    if (addressing) *addressing = ctx->mom ? -1 : ctx->mode;
+    return GMF_OK;
+}
+
+int gmf_get_tiling(gmf_ctx* ctx, int32_t* storage, int32_t* tile_x, int32_t* tile_y, int32_t* tile_z)
+{
+    if (!ctx) return GMF_ESTATE;
+    if (storage) *storage = ctx->mom ? GMF_STORE_MOMENTS : GMF_STORE_POPULATIONS;
+    if (tile_x) *tile_x = ctx->mom ? kMTileX[ctx->mtile] : 0;
+    if (tile_y) *tile_y = ctx->mom ? kMTileY[ctx->mtile] : 0;
+    if (tile_z) *tile_z = ctx->mom ? (int32_t)ctx->mtz : 0;
     return GMF_OK;
 }
 

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts():
     assert ctypes.sizeof(gmf.Replica) == 48
-    assert ctypes.sizeof(gmf.Options) == 32
+    assert ctypes.sizeof(gmf.Options) == 36
     # 3 int64 + 4 doubles + 3*10 doubles + 40 doubles + 16 int32
     assert ctypes.sizeof(gmf.Stats) == 8 * 3 + 8 * 4 + 8 * 30 + 8 * 40 + 4 * 16
 
@@ -70,6 +70,16 @@ def test_workspace_bytes_and_validation():
     assert _ws([(14, 10, 8, 1.0, 1.0, 1e-4, 1)], sample_every=5, spectrum=1) == 0  # factor 7
     assert _ws([(2048, 8, 8, 1.0, 1.0, 1e-4, 1)], sample_every=5, spectrum=1) == 0  # longer than 1024
     assert _ws([(12, 10, 8, 1.0, 1.0, 1e-4, 1)], sample_every=5, spectrum=2) == 0
+    # moment storage: two buffers of ten moments instead of 27 populations; GMF
+    # collision and the two-buffer scheme only
+    mom = _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], storage=gmf.STORE_MOMENTS)
+    assert 2 * 10 * 8 * 16 ** 3 <= mom <= ok - 2 * 17 * 8 * 16 ** 3
+    assert _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], storage=gmf.STORE_MOMENTS, streaming=gmf.STREAM_AB) == mom
+    assert _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], storage=gmf.STORE_MOMENTS, collision=gmf.COLLISION_BGK) == 0
+    assert _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], storage=gmf.STORE_MOMENTS, streaming=gmf.STREAM_AA) == 0
+    assert _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], storage=2) == 0
+    assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)], storage=gmf.STORE_MOMENTS, sample_every=10,
+               spectrum=1) > 2 * 10 * 8 * 512 ** 3
     # the 512^3 stress workload fits both precisions
     assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)]) > 2 * 27 * 8 * 512 ** 3
     assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)], precision=gmf.FP32_SHIFTED) > 0

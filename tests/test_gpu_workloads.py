@@ -233,3 +233,50 @@ def test_largest_box_1024cube_aa_with_sampling(tabs):
     assert abs(s1["mass"] - s0["mass"]) < 1e-6 * s0["mass"]
     assert np.all(np.abs(s1["momentum"]) < 1e-6 * s0["mass"])
     assert s1["nsamples"] == 3 and np.isfinite(s1["sum_var"]).all() and s1["sum_var"][0] > 0
+
+
+@pytest.mark.slow
+def test_spectral_equilibration_256cube():
+    """The Results-section measurement on the headline lattice: 256^3, k_BT 1e-4,
+    GMF-FLBM in FP32, tau in {0.6, 1, 5} batched in one context, 8000 warm-up
+    steps, then 10000 steps with the full-box spectra sampled every 10.  The
+    spectral ER_m(|k|) = S_m(|k|) / S_m^theory over the shells |k| = 4..64
+    (integer |n|): its mean over the shells is within 1% of 1, and its mean over
+    each octave band (4-7, 8-15, 16-31, 32-64) within 2% plus four standard
+    errors of that band.  The standard error is estimated from the decay of the
+    slow modes: a mode of wavenumber k relaxes at about nu k^2 (shear and, with
+    the bulk viscosity of a single relaxation time, sound alike), so the time
+    mean of its power over T steps has relative variance 1 / (nu k^2 T), and no
+    less than 1 / n_samples; k and -k are one mode of a real field.  At tau 0.6
+    this error is 1.4% for the lowest band and below 0.3% above it, so single
+    small shells (a few percent each) are not tested."""
+    kbt = 1e-4
+    taus = (0.6, 1.0, 5.0)
+    specs = [gmf.ReplicaSpec(256, 256, 256, 1.0, t, kbt, 11 + i) for i, t in enumerate(taus)]
+    flat = np.array([kbt / CS2, kbt, 3 * kbt, 5 * kbt, kbt])[:, None]
+    names = ("rho", "j", "jsum", "pdiag", "poff")
+    say("spectral ER at 256^3")
+    with gmf.Context(specs, precision=gmf.FP32_SHIFTED, sample_every=10, spectrum=1) as ctx:
+        ctx.step(8000)
+        ctx.reset_stats()
+        ctx.step(10000)
+        for r, t in enumerate(taus):
+            ns = ctx.stats(r)["nsamples"]
+            sums, cnt = ctx.spectrum(r)
+            er = sums[:, 4:65] / ns / flat
+            say(f"  tau={t}: ER min/max " + "  ".join(f"{names[m]} {er[m].min():.3f}/{er[m].max():.3f}" for m in range(5)) +
+                "; mean " + " ".join(f"{v:.4f}" for v in er.mean(axis=1)))
+            say("    rho ER by shell 4..12: " + " ".join(f"{v:.3f}" for v in er[0, :9]))
+            assert ns == 1000
+            assert np.all(np.abs(er.mean(axis=1) - 1) < 0.01), (t, er.mean(axis=1))
+            nu = (t - 0.5) * CS2
+            c = cnt[4:65]
+            shells = np.arange(4, 65)
+            k2 = (2 * np.pi * shells / 256) ** 2
+            rel_var = np.maximum(1.0 / (nu * k2 * 10000), 1.0 / ns)
+            for lo, hi in ((4, 8), (8, 16), (16, 32), (32, 65)):
+                sel = slice(lo - 4, hi - 4)
+                band = (er[:, sel] * c[sel]).sum(axis=1) / c[sel].sum()
+                sigma = np.sqrt(np.sum(2 * rel_var[sel] * c[sel])) / c[sel].sum()
+                say(f"    band {lo}-{hi - 1}: " + " ".join(f"{v:.4f}" for v in band) + f"  (standard error {sigma:.4f})")
+                assert np.all(np.abs(band - 1) < 0.02 + 4 * sigma), (t, lo, hi, band, sigma)

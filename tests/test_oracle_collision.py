@@ -110,6 +110,30 @@ def test_filter_matches_hydrodynamic_projector(tabs):
         np.testing.assert_allclose(oracle.collide(f, p), P @ f, atol=2e-16)
 
 
+@pytest.mark.parametrize("tau", [0.51, 0.8, 2.0])
+def test_gmf_collision_ignores_ghost_content(tabs, tau):
+    """Eq. (10) keeps no deterministic ghost content: adding any combination of
+    the ghost vectors w_i e_ki (k = 10..26) to f, which leaves rho, j and Pi
+    unchanged, leaves f* unchanged (noise included), so the ten hydrodynamic
+    moments of f are the whole state the GMF update depends on.  BGK (Eq. (1))
+    relaxes the ghosts and does not have this property."""
+    vel, w, e, b, *_ = tabs
+    rng = np.random.default_rng(int(tau * 100))
+    c = vel.astype(float)
+    for node in range(6):
+        f = _random_state(rng, w)
+        ghost = (w[:, None] * e[10:].T) @ rng.normal(scale=1e-3, size=17)
+        # the ghost directions carry no mass, momentum or stress
+        np.testing.assert_allclose([ghost.sum(), *(c.T @ ghost)], 0.0, atol=1e-17)
+        np.testing.assert_allclose(np.einsum("ia,ib,i->ab", c, c, ghost), 0.0, atol=1e-17)
+        pg = oracle.params(1, tau=tau, kbt=1e-4, seed=7)
+        a = oracle.collide(f, pg, node=node, step=5)
+        g = oracle.collide(f + ghost, pg, node=node, step=5)
+        assert np.max(np.abs(a - g)) < 1e-15
+        pb = oracle.params(1, tau=tau, kbt=1e-4, seed=7, collision=oracle.BGK)
+        assert np.max(np.abs(oracle.collide(f, pb, node=node, step=5) - oracle.collide(f + ghost, pb, node=node, step=5))) > 1e-6
+
+
 @pytest.mark.parametrize("coll", [oracle.GMF, oracle.BGK])
 @pytest.mark.parametrize("tau", [0.51, 0.7, 1.0, 3.0])
 def test_moment_space_reading_agrees(tabs, coll, tau):
