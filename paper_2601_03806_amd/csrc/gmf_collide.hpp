@@ -100,6 +100,39 @@ __device__ constexpr int kGhostSlot[17] = {
 // amplitude group of each ghost (index into RepDev::amp)
 __device__ constexpr int kGhostGroup[17] = {2, 2, 2, 2, 2, 2, 3, 4, 4, 4, 5, 5, 5, 6, 6, 6, 7};
 
+// Raw buffer access: a uniform 64-bit base in a buffer resource plus a 32-bit
+// vector offset (and a scalar one), so that no per-access 64-bit address
+// arithmetic is spent on the vector ALUs.  POLICY: cache-policy bits,
+// kNontemporal for data touched once per step, 0 for cached accesses.
+constexpr int kNontemporal = 2;   // cache-policy bits of the buffer builtins on gfx950
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base)
+{
+    // raw buffer: stride 0, 2^32 - 1 bytes addressable, gfx9 resource word 3
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, -1, 0x00020000);
+}
+
+template <typename T, int POLICY = kNontemporal>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    if constexpr (sizeof(T) == 4)
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, POLICY));
+    else
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, POLICY));
+}
+
+template <int POLICY = kNontemporal>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, POLICY);
+}
+template <int POLICY = kNontemporal>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double v)
+{
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, POLICY);
+}
+
 // The replica record is read once per workgroup and pinned in scalar
 // registers: the compiler cannot otherwise prove that fields re-read after
 // the first stores are uniform, and buffer offsets must be scalar.

@@ -42,13 +42,22 @@ struct StepArgs {
 //   0: rho - rho0, 1-3: j_x, j_y, j_z, 4-6: Pi_aa - rho0 cs2 (a = x, y, z),
 //   7: Pi_xy, 8: Pi_xz, 9: Pi_yz.
 constexpr int kMom = 10;
-// tile shapes (x, y) of the moment-storage step kernel; a workgroup has one
-// thread per column of the tile plus its one-node halo, rounded up to whole
-// wavefronts
-constexpr int kMTiles = 3;
-constexpr int kMTileX[kMTiles] = {64, 32, 32};
-constexpr int kMTileY[kMTiles] = {8, 16, 8};
-constexpr int mtile_threads(int t) { return ((kMTileX[t] + 2) * (kMTileY[t] + 2) + 63) / 64 * 64; }
+// tile shapes (x, y) of the moment-storage step kernel and threads per
+// workgroup: one per column of the tile plus its one-node halo rounded up to
+// whole wavefronts, at most 1024 (larger haloed tiles take two rounds of
+// columns per thread)
+constexpr int kMTiles = 4;
+constexpr int kMTileX[kMTiles] = {64, 32, 32, 64};
+constexpr int kMTileY[kMTiles] = {8, 16, 8, 16};
+// LDS of one workgroup (the 27 post-collision populations of the haloed tile)
+// and whether it fits the 160 KiB of a gfx950 CU, for values of es bytes
+constexpr size_t mtile_lds_bytes(int t, size_t es) { return (size_t)Q * (kMTileX[t] + 2) * (kMTileY[t] + 2) * es; }
+constexpr bool mtile_fits(int t, size_t es) { return mtile_lds_bytes(t, es) <= 160u * 1024u; }
+constexpr int mtile_threads(int t)
+{
+    return ((kMTileX[t] + 2) * (kMTileY[t] + 2) + 63) / 64 * 64 > 1024 ? 1024
+                                                                      : ((kMTileX[t] + 2) * (kMTileY[t] + 2) + 63) / 64 * 64;
+}
 
 // lattice kernels
 // sm: streaming pattern kAB, kAAPull or kAALocal (gmf_device.hpp); the AA

@@ -26,45 +26,12 @@ namespace gmf {
 // ---------------------------------------------------------------------------
 // The fused stream + collide step
 // ---------------------------------------------------------------------------
-// Population traffic goes through raw buffer instructions: one resource per
-// storage group (uniform), the population's row start as scalar offset and the
-// node's row/x offset as 32-bit vector offset, so no per-access 64-bit address
-// arithmetic is spent on the vector ALUs.  Every population value is read and
-// written exactly once per step: the accesses are marked nontemporal.
-constexpr int kNontemporal = 2;   // cache-policy bits of the buffer builtins on gfx950
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base)
-{
-    // raw buffer: stride 0, 2^32 - 1 bytes addressable, gfx9 resource word 3
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, -1, 0x00020000);
-}
-
-template <typename T>
-__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
-template <>
-__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
-{
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, kNontemporal));
-}
-template <>
-__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kNontemporal));
-}
-
-// POLICY: kNontemporal, or 0 (cached) for rows written shifted by one node in x,
-// whose partly covered cache lines the L2 then completes before writing back
-template <int POLICY = kNontemporal>
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, POLICY);
-}
-template <int POLICY = kNontemporal>
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, double v)
-{
-    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, POLICY);
-}
+// Population traffic goes through raw buffer instructions (gmf_collide.hpp):
+// one resource per storage group (uniform), the population's row start as
+// scalar offset and the node's row/x offset as 32-bit vector offset, so no
+// per-access 64-bit address arithmetic is spent on the vector ALUs.  Every
+// population value is read and written exactly once per step: the accesses
+// are marked nontemporal.
 
 // resource of the storage group holding population p, and p's row-start offset in it (bytes)
 template <typename T, int G>
@@ -197,7 +164,8 @@ __device__ __forceinline__ void node_update(const StepArgs& a, const RepDev& R, 
 
     if constexpr (SM == kAAPull) {
         // f*_p goes where f_(26-p) came from: population 26 - p at x + c_p
-        // (rows shifted in x are written through the cache, see bstore)
+        // (rows shifted by one node in x are written through the cache, policy 0:
+        // the L2 completes their partly covered lines before writing them back)
         if constexpr (G == kPlane) {
 #pragma unroll
             for (int p = 0; p < Q; ++p) {

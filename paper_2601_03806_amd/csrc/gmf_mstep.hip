@@ -52,9 +52,12 @@ __device__ __forceinline__ void post_collision(const Hydro<T>& h, const RepDev& 
 
 // Adds to A the raw moments of the nine populations with z velocity CZ that
 // streamed into a node, g[3 (cx+1) + (cy+1)]: separable sums over cx, then cy.
-template <typename T, int CZ>
+// FIRST (CZ = +1 only, the first contribution a destination receives): A is
+// assigned instead.
+template <typename T, int CZ, bool FIRST = false>
 __device__ __forceinline__ void add_slice(Hydro<T>& A, const T g[9])
 {
+    static_assert(!FIRST || CZ == 1, "only the c_z = +1 slice comes first");
     T X0[3], X1[3], X2[3];
 #pragma unroll
     for (int cy = 0; cy < 3; ++cy) {
@@ -69,6 +72,10 @@ __device__ __forceinline__ void add_slice(Hydro<T>& A, const T g[9])
     const T sx = X1[0] + X1[1] + X1[2];
     const T sxy = X1[2] - X1[0];
     const T sxx = X2[0] + X2[1] + X2[2];
+    if (FIRST) {
+        A = Hydro<T>{s, sx, sy, s, sxx, syy, s, sxy, sx, sy};
+        return;
+    }
     A.s0 += s;
     A.jx += sx;
     A.jy += sy;
@@ -95,10 +102,12 @@ __device__ __forceinline__ Hydro<T> zero_hydro()
     return Hydro<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
 }
 
-template <typename T, bool SAMPLE, int TX, int TY>
-__global__ __launch_bounds__(((TX + 2) * (TY + 2) + 63) / 64 * 64) void mstep_kernel(const StepArgs a)
+template <typename T, bool SAMPLE, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void mstep_kernel(const StepArgs a)
 {
     constexpr int EX = TX + 2, EY = TY + 2, NE = EX * EY;
+    constexpr int NR = (NE + NT - 1) / NT;   // haloed columns per thread
+    static_assert(TX * TY <= NT, "one tile column per thread in the gather");
     __shared__ T lds[Q * NE];
 
     // workgroup -> tile, with the same XCD mappings as the population step
@@ -121,46 +130,68 @@ __global__ __launch_bounds__(((TX + 2) * (TY + 2) + 63) / 64 * 64) void mstep_ke
     const uint32_t z1 = min(z0 + a.tz, nz);
     const int nplanes = (int)(z1 - z0) + 2;
 
-    // the column this thread collides: e = ey EX + ex of the haloed tile, at
-    // (x0 + ex - 1, y0 + ey - 1) mod the box
-    const uint32_t e = threadIdx.x;
-    const bool collider = e < (uint32_t)NE;
-    const uint32_t ex = e % EX, ey = e / EX;
-    const uint32_t col = ((y0 + ey + ny - 1) % ny) * nx + (x0 + ex + nx - 1) % nx;
-    const bool inner = SAMPLE && collider && ex >= 1 && ex <= (uint32_t)TX && ey >= 1 && ey <= (uint32_t)TY &&
-                       x0 + ex - 1 < nx && y0 + ey - 1 < ny;
+    // the columns this thread collides: e = threadIdx.x + q NT = ey EX + ex of
+    // the haloed tile, at (x0 + ex - 1, y0 + ey - 1) mod the box; moments move
+    // through buffer resources (per field and plane a uniform base, per column
+    // a fixed 32-bit offset; loads cached, so that the halo columns that
+    // neighbouring tiles read again come from the L2)
+    uint32_t col[NR], vcol[NR];
+    bool inner[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const uint32_t e = threadIdx.x + (uint32_t)(q * NT);
+        const uint32_t ex = e % EX, ey = e / EX;
+        col[q] = ((y0 + ey + ny - 1) % ny) * nx + (x0 + ex + nx - 1) % nx;   // in the box for any e
+        vcol[q] = col[q] * (uint32_t)sizeof(T);
+        inner[q] = SAMPLE && e < (uint32_t)NE && ex >= 1 && ex <= (uint32_t)TX && ey >= 1 && ey <= (uint32_t)TY &&
+                   x0 + ex - 1 < nx && y0 + ey - 1 < ny;
+    }
     // the tile column this thread gathers into (threads 0 .. TX TY - 1)
     const uint32_t ix = threadIdx.x % TX, iy = threadIdx.x / TX;
     const bool gatherer = threadIdx.x < (uint32_t)(TX * TY);
     const bool owner = gatherer && x0 + ix < nx && y0 + iy < ny;
-    const uint32_t own = (y0 + iy) * nx + (x0 + ix);
+    const uint32_t vown = ((y0 + iy) * nx + (x0 + ix)) * (uint32_t)sizeof(T);
     const uint32_t e0 = (iy + 1) * EX + ix + 1;
 
     const T* src = reinterpret_cast<const T*>(a.src) + R.pop_offset;
     T* dst = reinterpret_cast<T*>(a.dst) + R.pop_offset;
-
     // source plane k of the march is z0 - 1 + k (periodic)
     auto src_plane = [&](int k) { return (z0 + (uint32_t)k + nz - 1) % nz; };
-    auto load = [&](int k, T (&m)[kMom]) {
-        const T* p = src + (uint64_t)src_plane(k) * plane + col;
+    auto load = [&](int k, T (&m)[NR][kMom]) {
+        const T* base = src + (uint64_t)src_plane(k) * plane;
 #pragma unroll
-        for (int f = 0; f < kMom; ++f) m[f] = collider ? p[(uint64_t)f * N] : T(0);
+        for (int f = 0; f < kMom; ++f) {
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(base + (uint64_t)f * N);
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                if (q == 0 || threadIdx.x + (uint32_t)(q * NT) < (uint32_t)NE) m[q][f] = bload<T, 0>(rs, vcol[q], 0);
+        }
     };
 
-    Hydro<T> am = zero_hydro<T>(), a0 = zero_hydro<T>(), ap = zero_hydro<T>();   // planes s-1, s, s+1
-    T mn[kMom];
+    // accumulators of the destination planes s-1 (am), s (a0), s+1 (ap)
+    Hydro<T> am = zero_hydro<T>(), a0 = zero_hydro<T>(), ap = zero_hydro<T>();
+    T mn[NR][kMom];
     load(0, mn);
     for (int k = 0; k < nplanes; ++k) {
-        const Hydro<T> h{mn[0], mn[1], mn[2], mn[3], mn[4], mn[5], mn[6], mn[7], mn[8], mn[9]};
+        T mc[NR][kMom];
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+#pragma unroll
+            for (int f = 0; f < kMom; ++f) mc[q][f] = mn[q][f];
         if (k + 1 < nplanes) load(k + 1, mn);
         const uint32_t sz = src_plane(k);
-        if (collider) {
-            const uint32_t n = sz * plane + col;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const uint32_t e = threadIdx.x + (uint32_t)(q * NT);
+            if (e >= (uint32_t)NE) continue;
+            const Hydro<T> h{mc[q][0], mc[q][1], mc[q][2], mc[q][3], mc[q][4],
+                             mc[q][5], mc[q][6], mc[q][7], mc[q][8], mc[q][9]};
+            const uint32_t n = sz * plane + col[q];
             T F[Q];
             post_collision<T>(h, R, n, t, F);
 #pragma unroll
             for (int p = 0; p < Q; ++p) lds[p * NE + e] = F[p];
-            if (SAMPLE && inner && k >= 1 && k <= nplanes - 2) {
+            if (SAMPLE && inner[q] && k >= 1 && k <= nplanes - 2) {
                 // fields of the sampled state f(., t) at a node of the tile
                 T* fl = reinterpret_cast<T*>(a.fields) + R.field_offset + n;
                 fl[0] = h.s0;
@@ -173,7 +204,8 @@ __global__ __launch_bounds__(((TX + 2) * (TY + 2) + 63) / 64 * 64) void mstep_ke
         }
         __syncthreads();
         if (gatherer) {
-            // population p = (cx, cy, cz) reaching this column left column (ix - cx, iy - cy)
+            // population p = (cx, cy, cz) reaching this column left column (ix - cx, iy - cy);
+            // the c_z = +1 slice is the first that plane s+1 receives
             T g[9];
 #pragma unroll
             for (int cz = 0; cz < 3; ++cz) {
@@ -184,24 +216,16 @@ __global__ __launch_bounds__(((TX + 2) * (TY + 2) + 63) / 64 * 64) void mstep_ke
                         g[3 * cx + cy] = lds[(9 * cx + 3 * cy + cz) * NE + e0 - (cy - 1) * EX - (cx - 1)];
                 if (cz == 0) add_slice<T, -1>(am, g);
                 if (cz == 1) add_slice<T, 0>(a0, g);
-                if (cz == 2) add_slice<T, 1>(ap, g);
+                if (cz == 2) add_slice<T, 1, true>(ap, g);
             }
             if (k >= 2 && owner) {
-                T* o = dst + (uint64_t)(z0 + (uint32_t)k - 2) * plane + own;
-                __builtin_nontemporal_store(am.s0, o);
-                __builtin_nontemporal_store(am.jx, o + N);
-                __builtin_nontemporal_store(am.jy, o + 2 * N);
-                __builtin_nontemporal_store(am.jz, o + 3 * N);
-                __builtin_nontemporal_store(am.pxx, o + 4 * N);
-                __builtin_nontemporal_store(am.pyy, o + 5 * N);
-                __builtin_nontemporal_store(am.pzz, o + 6 * N);
-                __builtin_nontemporal_store(am.pxy, o + 7 * N);
-                __builtin_nontemporal_store(am.pxz, o + 8 * N);
-                __builtin_nontemporal_store(am.pyz, o + 9 * N);
+                T* base = dst + (uint64_t)(z0 + (uint32_t)k - 2) * plane;
+                const T v[kMom] = {am.s0, am.jx, am.jy, am.jz, am.pxx, am.pyy, am.pzz, am.pxy, am.pxz, am.pyz};
+#pragma unroll
+                for (int f = 0; f < kMom; ++f) bstore(make_rsrc(base + (uint64_t)f * N), vown, 0, v[f]);
             }
             am = a0;
             a0 = ap;
-            ap = zero_hydro<T>();
         }
         __syncthreads();
     }
@@ -210,6 +234,9 @@ __global__ __launch_bounds__(((TX + 2) * (TY + 2) + 63) / 64 * 64) void mstep_ke
 template <typename T, bool SAMPLE, int TILE>
 static hipError_t launch_mstep_tile(const StepArgs& a, uint32_t nblocks, hipStream_t s)
 {
+    if constexpr (!mtile_fits(TILE, sizeof(T))) {
+        return hipErrorInvalidValue;
+    } else {
     StepArgs b = a;
     b.nblocks = nblocks;
     uint32_t g = nblocks;
@@ -217,8 +244,9 @@ static hipError_t launch_mstep_tile(const StepArgs& a, uint32_t nblocks, hipStre
         b.chunk = a.chunk ? a.chunk : (nblocks + a.xcd - 1u) / a.xcd;
         g = (nblocks + a.xcd * b.chunk - 1u) / (a.xcd * b.chunk) * b.chunk * a.xcd;
     }
-    mstep_kernel<T, SAMPLE, kMTileX[TILE], kMTileY[TILE]><<<g, mtile_threads(TILE), 0, s>>>(b);
+    mstep_kernel<T, SAMPLE, kMTileX[TILE], kMTileY[TILE], mtile_threads(TILE)><<<g, mtile_threads(TILE), 0, s>>>(b);
     return hipGetLastError();
+    }
 }
 
 template <typename T, bool SAMPLE>
@@ -228,6 +256,7 @@ static hipError_t launch_mstep_t(int tile, const StepArgs& a, uint32_t nblocks, 
     case 0: return launch_mstep_tile<T, SAMPLE, 0>(a, nblocks, s);
     case 1: return launch_mstep_tile<T, SAMPLE, 1>(a, nblocks, s);
     case 2: return launch_mstep_tile<T, SAMPLE, 2>(a, nblocks, s);
+    case 3: return launch_mstep_tile<T, SAMPLE, 3>(a, nblocks, s);
     default: return hipErrorInvalidValue;
     }
 }

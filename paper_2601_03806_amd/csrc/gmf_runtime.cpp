@@ -35,7 +35,7 @@ constexpr int kXcdMaps = 3;
 constexpr uint32_t kXcdChunks[kXcdMaps] = {0u, 0u, 16u};
 // moment storage: z planes per tile tried by the autotuner, and the default tile
 constexpr int kMTzCount = 4;
-constexpr uint32_t kMTz[kMTzCount] = {8u, 16u, 32u, 64u};
+constexpr uint32_t kMTz[kMTzCount] = {16u, 32u, 64u, 128u};
 constexpr int kDefaultMTile = 0;
 constexpr uint32_t kDefaultMTz = 32u;
 
@@ -640,7 +640,8 @@ int autotune_moments(gmf_ctx* ctx)
             char k[4096];
             int tl, tz, xm, unused;
             while (fscanf(fh, "%4095s %d %d %d %d", k, &tl, &tz, &xm, &unused) == 5)
-                if (key == k && tl >= 0 && tl < kMTiles && tz >= 1 &&
+                if (key == k && tl >= 0 && tl < kMTiles && tz >= (int)kMTz[0] &&
+                    mtile_fits(tl, ctx->opt.precision == GMF_FP32_SHIFTED ? 4 : 8) &&
                     std::find(maps.begin(), maps.end(), xm) != maps.end()) {
                     best_tile = tl;
                     best_tz = (uint32_t)tz;
@@ -661,9 +662,11 @@ int autotune_moments(gmf_ctx* ctx)
             float ms;
         };
         std::vector<Cand> cands;
+        const size_t es = ctx->opt.precision == GMF_FP32_SHIFTED ? 4 : 8;
         for (int tl = 0; tl < kMTiles; ++tl)
             for (uint32_t tz : kMTz)
-                for (int xm : maps) cands.push_back({tl, tz, xm, 1e30f});
+                for (int xm : maps)
+                    if (mtile_fits(tl, es)) cands.push_back({tl, tz, xm, 1e30f});
         const int reps = 8;
         for (int round = 0; round < 2; ++round) {
             for (Cand& cd : cands) {
@@ -799,7 +802,8 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
     // GMF_MTILE = "tile,depth" forces the moment-storage tile (tests)
     if (const char* forced = getenv("GMF_MTILE")) {
         int tl = -1, tz = 0;
-        if (sscanf(forced, "%d,%d", &tl, &tz) == 2 && tl >= 0 && tl < kMTiles && tz >= (int)kMTz[0]) {
+        if (sscanf(forced, "%d,%d", &tl, &tz) == 2 && tl >= 0 && tl < kMTiles && tz >= (int)kMTz[0] &&
+            mtile_fits(tl, opt.precision == GMF_FP32_SHIFTED ? 4 : 8)) {
             ctx->mtile = tl;
             ctx->mtz = (uint32_t)tz;
         }
