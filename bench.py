@@ -29,9 +29,18 @@ MOM_BYTES_PER_NODE = {"fp32": 80, "fp64": 160}  # moment storage: 10 loads + 10 
 METRIC = "GLUPS & % HBM roofline, FP32-batched vs FP64-plain, at matched variance accuracy"
 
 
-def kernel_source_hash() -> str:
+# sources of each step kernel: a committed counter profile counts for the
+# kernel only while these files are unchanged
+KERNEL_SOURCES = {
+    "step": ("gmf_kernels.hip", "gmf_collide.hpp", "gmf_device.hpp", "gmf_math.hpp", "gmf_internal.hpp"),
+    "mstep": ("gmf_mstep.hip", "gmf_collide.hpp", "gmf_device.hpp", "gmf_math.hpp", "gmf_internal.hpp"),
+}
+VALU_PEAK = 256 * 4 * 2.4e9 / 4 / 1e9   # wave64 VALU instructions per ns: 256 CUs x 4 SIMDs, one per 4 cycles
+
+
+def kernel_source_hash(kernel: str = "step") -> str:
     h = hashlib.sha256()
-    for f in ("gmf_kernels.hip", "gmf_collide.hpp", "gmf_device.hpp", "gmf_math.hpp"):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2601_03806_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -39,13 +48,15 @@ def kernel_source_hash() -> str:
 
 def variant_key(cfg: dict) -> str:
     """Step-kernel variant as named in profiles/traffic.json."""
+    if cfg.get("storage") == "moments":
+        return f"moments/{cfg['tile']}/{cfg['block_map']}"
     return f"{cfg['addressing']}/{cfg['streaming']}/npt{cfg['nodes_per_thread']}/{cfg['block_map']}"
 
 
-def measured_traffic(kernel_key: str, nodes: int, cfg: dict):
-    """HBM bytes per launch of the step-kernel variant that ran, from the
-    committed rocprofv3 counter summary, if it was taken on the current kernel
-    source; else None."""
+def profiled(kernel_key: str, nodes: int, cfg: dict, field: str = "bytes_per_launch"):
+    """A per-launch figure (HBM bytes, VALU instructions) of the step-kernel
+    variant that ran, from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -53,10 +64,11 @@ def measured_traffic(kernel_key: str, nodes: int, cfg: dict):
     except (OSError, ValueError):
         return None
     ent = data.get(kernel_key)
-    if not ent or ent.get("source_hash") != kernel_source_hash() or ent.get("nodes") != nodes:
+    kernel = "mstep" if kernel_key.startswith("mstep") else "step"
+    if not ent or ent.get("source_hash") != kernel_source_hash(kernel) or ent.get("nodes") != nodes:
         return None
     var = ent.get("variants", {}).get(variant_key(cfg))
-    return None if var is None else var.get("bytes_per_launch")
+    return None if var is None else var.get(field)
 
 
 def time_context(ctx, stream, steps, warmup, torch):
@@ -78,8 +90,10 @@ def run_gpu(args, torch, gmf, wl):
     w = wl.bandwidth_headline("fp32")
     b = w.boxes[0]
     spec = gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed)
-    with gmf.Context([spec], precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune) as ctx:
-        print(f"[bench] fp32 {w.name}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+    storage = gmf.STORE_MOMENTS if args.storage == "moments" else gmf.STORE_POPULATIONS
+    with gmf.Context([spec], precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune, storage=storage) as ctx:
+        print(f"[bench] fp32 {w.name} ({args.storage}): warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
+              flush=True)
         sec = time_context(ctx, stream, args.steps, args.warmup, torch)
         st = ctx.stats()
         out["fp32"] = {"seconds": sec, "nodes": spec.n, "steps": args.steps, "config": ctx.config(),
@@ -103,6 +117,13 @@ def run_gpu(args, torch, gmf, wl):
             sec = time_context(ctx, stream, se, args.warmup, torch)
             out["batched"] = {"seconds": sec, "nodes": we.nodes, "steps": se, "config": ctx.config(),
                               "workload": we.name}
+        torch.cuda.synchronize()
+        with gmf.Context(specs, precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune,
+                         storage=gmf.STORE_MOMENTS) as ctx:
+            print(f"[bench] batched {we.name}, moment storage: steps {se}", file=sys.stderr, flush=True)
+            sec = time_context(ctx, stream, se, args.warmup, torch)
+            out["batched_mom"] = {"seconds": sec, "nodes": we.nodes, "steps": se, "config": ctx.config(),
+                                  "workload": we.name}
         torch.cuda.synchronize()
         # the headline box with the in-place AA pattern (one population buffer: half the memory)
         with gmf.Context([spec], precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune,
@@ -210,6 +231,8 @@ def main():
     ap.add_argument("--tune", type=int, default=1, help="1: autotune the kernel variant at init (default)")
     ap.add_argument("--skip-extra", action="store_true", help="only the FP32 headline (profiling runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--storage", choices=("populations", "moments"), default="populations",
+                    help="storage of the FP32 256^3 headline run (moments: profiling of the moment-storage kernel)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain device copy of one population buffer (bandwidth reference)")
     args = ap.parse_args()
@@ -239,7 +262,8 @@ def main():
     # launch duration, i.e. the events around the timed region over its launches
     # (the captured step loop launches the step kernel back to back)
     kernel_s = r32["seconds"] / r32["steps"]
-    achieved = BYTES_PER_NODE["fp32"] * r32["nodes"] / kernel_s / 1e9
+    bpn = (MOM_BYTES_PER_NODE if args.storage == "moments" else BYTES_PER_NODE)["fp32"]
+    achieved = bpn * r32["nodes"] / kernel_s / 1e9
     line = {
         "metric": METRIC,
         "value": round(glups, 4),
@@ -255,12 +279,14 @@ def main():
         "data": "synthetic (equilibrium fluid at rest, rho0=1, Philox noise)",
         "config": {"workload": "d3q27_256cube_fp32_tau0.8", "lattice": [256, 256, 256], "rho0": 1.0,
                    "tau": 0.8, "kbt": 1e-4, "seed": 1, "precision": "fp32_shifted",
-                   "layout": "row-interleaved populations, " + ("in-place AA" if r32["config"]["streaming"] == "AA"
-                                                                   else "A/B pull"),
+                   "layout": ("ten moments per node, A/B" if args.storage == "moments" else
+                              "row-interleaved populations, " + ("in-place AA" if r32["config"]["streaming"] == "AA"
+                                                                 else "A/B pull")),
                    "kernel_config": r32["config"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("step_fp32_256", r32["nodes"], r32["config"])},
+                     "traffic": profiled("mstep_fp32_256" if args.storage == "moments" else "step_fp32_256",
+                                         r32["nodes"], r32["config"])},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "mass_drift_rel": r32["mass_drift_rel"],
     }
@@ -280,6 +306,13 @@ def main():
                                 "ms_per_step": round(r["seconds"] / r["steps"] * 1e3, 5),
                                 "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                                 "steps": r["steps"], "kernel_config": r["config"]}
+    if "batched_mom" in res:
+        r = res["batched_mom"]
+        g = r["nodes"] * r["steps"] / r["seconds"] / 1e9
+        line["fp32_batched_moment_storage"] = {"workload": r["workload"] + ", moment storage", "replicas": 64,
+                                               "glups": round(g, 4),
+                                               "ms_per_step": round(r["seconds"] / r["steps"] * 1e3, 5),
+                                               "steps": r["steps"], "kernel_config": r["config"]}
     if "aa" in res:
         r = res["aa"]
         g = r["nodes"] * r["steps"] / r["seconds"] / 1e9
@@ -317,6 +350,16 @@ def main():
                 "glups": round(g, 4), "ms_per_step": round(r["seconds"] / r["steps"] * 1e3, 5),
                 "gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                 "steps": r["steps"], "kernel_config": r["config"]}
+            if bpn == "fp32":
+                # the kernel is bound by its vector ALU work: VALU instructions per
+                # launch (committed counter profile) over the live launch time
+                valu = profiled("mstep_fp32_256", r["nodes"], r["config"], "valu_insts_per_launch")
+                ns = r["seconds"] / r["steps"] * 1e9
+                line[f"{bpn}_moment_storage"]["roofline"] = {
+                    "bound": "alu", "unit": "wave64 VALU instructions per ns", "peak": VALU_PEAK,
+                    "achieved": None if valu is None else round(valu / ns, 1),
+                    "frac": None if valu is None else round(valu / ns / VALU_PEAK, 4),
+                    "traffic": profiled("mstep_fp32_256", r["nodes"], r["config"])}
     if not args.no_cpu and int(os.environ.get("RANK", 0)) == 0:
         print("[bench] oracle timing on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline()

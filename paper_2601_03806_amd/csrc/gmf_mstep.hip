@@ -108,7 +108,11 @@ __global__ __launch_bounds__(NT) void mstep_kernel(const StepArgs a)
     constexpr int EX = TX + 2, EY = TY + 2, NE = EX * EY;
     constexpr int NR = (NE + NT - 1) / NT;   // haloed columns per thread
     static_assert(TX * TY <= NT, "one tile column per thread in the gather");
-    __shared__ T lds[Q * NE];
+    // two LDS buffers when they fit: consecutive planes alternate between them,
+    // so one barrier per plane suffices (a wave rewrites a buffer only after
+    // the next plane's barrier, which every wave reaches after its reads)
+    constexpr int NB = 2 * Q * NE * sizeof(T) <= 160 * 1024 ? 2 : 1;
+    __shared__ T lds[NB * Q * NE];
 
     // workgroup -> tile, with the same XCD mappings as the population step
     uint32_t blk = blockIdx.x;
@@ -173,6 +177,7 @@ __global__ __launch_bounds__(NT) void mstep_kernel(const StepArgs a)
     T mn[NR][kMom];
     load(0, mn);
     for (int k = 0; k < nplanes; ++k) {
+        T* buf = lds + (NB == 2 ? (k & 1) * Q * NE : 0);
         T mc[NR][kMom];
 #pragma unroll
         for (int q = 0; q < NR; ++q)
@@ -190,7 +195,7 @@ __global__ __launch_bounds__(NT) void mstep_kernel(const StepArgs a)
             T F[Q];
             post_collision<T>(h, R, n, t, F);
 #pragma unroll
-            for (int p = 0; p < Q; ++p) lds[p * NE + e] = F[p];
+            for (int p = 0; p < Q; ++p) buf[p * NE + e] = F[p];
             if (SAMPLE && inner[q] && k >= 1 && k <= nplanes - 2) {
                 // fields of the sampled state f(., t) at a node of the tile
                 T* fl = reinterpret_cast<T*>(a.fields) + R.field_offset + n;
@@ -213,7 +218,7 @@ __global__ __launch_bounds__(NT) void mstep_kernel(const StepArgs a)
                 for (int cx = 0; cx < 3; ++cx)
 #pragma unroll
                     for (int cy = 0; cy < 3; ++cy)
-                        g[3 * cx + cy] = lds[(9 * cx + 3 * cy + cz) * NE + e0 - (cy - 1) * EX - (cx - 1)];
+                        g[3 * cx + cy] = buf[(9 * cx + 3 * cy + cz) * NE + e0 - (cy - 1) * EX - (cx - 1)];
                 if (cz == 0) add_slice<T, -1>(am, g);
                 if (cz == 1) add_slice<T, 0>(a0, g);
                 if (cz == 2) add_slice<T, 1, true>(ap, g);
@@ -227,7 +232,7 @@ __global__ __launch_bounds__(NT) void mstep_kernel(const StepArgs a)
             am = a0;
             a0 = ap;
         }
-        __syncthreads();
+        if (NB == 1) __syncthreads();
     }
 }
 

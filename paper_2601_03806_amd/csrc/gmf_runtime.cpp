@@ -36,8 +36,8 @@ constexpr uint32_t kXcdChunks[kXcdMaps] = {0u, 0u, 16u};
 // moment storage: z planes per tile tried by the autotuner, and the default tile
 constexpr int kMTzCount = 4;
 constexpr uint32_t kMTz[kMTzCount] = {16u, 32u, 64u, 128u};
-constexpr int kDefaultMTile = 0;
-constexpr uint32_t kDefaultMTz = 32u;
+constexpr int kDefaultMTile = 1;
+constexpr uint32_t kDefaultMTz = 64u;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -627,12 +627,17 @@ int autotune(gmf_ctx* ctx)
 int autotune_moments(gmf_ctx* ctx)
 {
     const char* cache = getenv("GMF_TUNE_CACHE");
-    std::string key = "m1p" + std::to_string(ctx->opt.precision);
+    std::string key = "m2p" + std::to_string(ctx->opt.precision);
     for (auto& r : ctx->reps) key += "_" + std::to_string(r.nx) + "x" + std::to_string(r.ny) + "x" + std::to_string(r.nz);
-    std::vector<int> maps = {0};
+    // the halo columns a tile reads again are L2 hits only when neighbouring
+    // tiles run on the same XCD: with several XCDs only the XCD mappings are
+    // tried (the linear one measured 1.66x the algorithmic reads at 256^3)
+    std::vector<int> maps;
     if (ctx->xcd_count > 1)
         for (int xm = 1; xm < kXcdMaps; ++xm) maps.push_back(xm);
-    int best_tile = ctx->mtile, best_map = ctx->xcd_map;
+    else
+        maps.push_back(0);
+    int best_tile = ctx->mtile, best_map = maps.front();
     uint32_t best_tz = ctx->mtz;
     bool cached = false;
     if (cache) {
@@ -815,6 +820,9 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         else
             (void)hipGetLastError();
     }
+    // moment storage reads the halo columns of a tile again: by default each
+    // XCD takes runs of neighbouring tiles, so that those reads hit its L2
+    if (ctx->mom && ctx->xcd_count > 1) ctx->xcd_map = 2;
     // GMF_BLOCK_MAP = linear | xcd | xcd16 forces the workgroup-to-block mapping (tests)
     if (const char* forced = getenv("GMF_BLOCK_MAP")) {
         ctx->xcd_map = 0;

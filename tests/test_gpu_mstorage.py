@@ -287,3 +287,29 @@ def test_moment_storage_option_errors():
     for kw in ({"collision": gmf.COLLISION_BGK}, {"streaming": gmf.STREAM_AA}):
         with pytest.raises(gmf.GmfError):
             gmf.Context([spec], storage=MOM, **kw)
+
+
+@pytest.mark.slow
+def test_moment_storage_tau_sweep_statistics():
+    """64^3 at tau in {0.51, 0.6, 1, 2, 5}, k_B T = 1e-4, 2000 warm-up + 20000
+    steps sampled every 10: the FP32 moment-storage variances and shell spectra
+    are within 1% of FP64 population storage with the same seeds (paired noise),
+    the bar that FP32 population storage meets."""
+    w32 = wl.tau_sweep("fp32")
+    specs = [gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed) for b in w32.boxes]
+    out = {}
+    for prec, st in ((gmf.FP32_SHIFTED, MOM), (gmf.FP64, gmf.STORE_POPULATIONS)):
+        say(f"moment storage tau sweep prec={prec} storage={st}")
+        with gmf.Context(specs, precision=prec, sample_every=w32.sample_every, storage=st) as ctx:
+            ctx.step(w32.warmup)
+            ctx.reset_stats()
+            ctx.step(w32.steps)
+            out[st] = [ctx.stats(r) for r in range(len(specs))]
+    for r, s in enumerate(specs):
+        a, b = out[MOM][r], out[gmf.STORE_POPULATIONS][r]
+        assert a["nsamples"] == b["nsamples"] == w32.steps // w32.sample_every
+        ratio = (a["sum_var"] / a["nsamples"]) / (b["sum_var"] / b["nsamples"])
+        sratio = a["spectrum"] / b["spectrum"]
+        say(f"  tau={s.tau}: variance ratios {np.round(ratio, 4)}; spectra {sratio.min():.4f}..{sratio.max():.4f}")
+        assert np.all(np.abs(ratio - 1) < 0.01), (s.tau, ratio)
+        assert np.all(np.abs(sratio - 1) < 0.01), (s.tau, sratio)
