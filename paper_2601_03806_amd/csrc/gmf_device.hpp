@@ -214,7 +214,7 @@ struct Normal<double> {
         const double u1 = ((double)a + 0.5) * 0x1p-32;
         const double u2 = ((double)b + 0.5) * 0x1p-32;
         // logarithm and sine/cosine specialised to these arguments (gmf_math.hpp)
-        const double rad = sqrt(-2.0 * fp64::log_unit(u1));
+        const double rad = fp64::sqrt_pos(-2.0 * fp64::log_unit(u1));
         double s, c;
         fp64::sincos_2pi(u2, &s, &c);
         r0 = rad * c;
