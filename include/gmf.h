@@ -229,11 +229,13 @@ int gmf_noise_probe(uint64_t seed, int64_t t, uint32_t node0, int32_t count, int
 /* Kernel configuration in use (for reports): nodes per thread, threads per
  * workgroup, steps per captured HIP graph (0: direct launches), the
  * addressing mode of the step kernel (0: plane-uniform rows of 27 populations;
- * 27, 3, 1: per-node addressing with storage groups of that many populations),
- * the streaming pattern (GMF_STREAM_AB or GMF_STREAM_AA), and the workgroup
- * mapping (0: workgroup b updates lattice block b, so consecutive blocks go to
- * different XCDs; C > 0: each XCD updates runs of C consecutive blocks of 256
- * or 512 nodes).  Any output pointer may be NULL. */
+ * 27, 3, 1: per-node addressing with storage groups of that many populations;
+ * -1 with moment storage), the streaming pattern (GMF_STREAM_AB or
+ * GMF_STREAM_AA; moment storage alternates two buffers like GMF_STREAM_AB), and
+ * the workgroup mapping (0: workgroup b updates lattice block b, so consecutive
+ * blocks go to different XCDs; C > 0: each XCD updates runs of C consecutive
+ * blocks, of 256 or 512 nodes, or tiles with moment storage).  Any output
+ * pointer may be NULL. */
 int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int32_t* graphs, int32_t* addressing,
                    int32_t* streaming, int32_t* xcd_map);
 /* Storage kind in use (GMF_STORE_*) and, for moment storage, the tile of one
