@@ -249,37 +249,65 @@ def _neighbour(n, c, spec):
     return ((x + c[0]) % spec.nx) + spec.nx * (((y + c[1]) % spec.ny) + spec.ny * ((z + c[2]) % spec.nz))
 
 
-@pytest.mark.parametrize("precision,tol", [(gmf.FP32_SHIFTED, 3e-5), (gmf.FP64, 1e-12)])
-def test_full_size_sampled_nodes_vs_oracle(tabs, precision, tol):
-    """256^3, tau 0.8, k_BT 1e-4, seed 1, autotuned tiling and graph step loop
-    (the benchmark's configuration): after 64 steps, one more step at sampled
-    nodes x: the oracle collides the 27 neighbours x - c_i (their populations
-    from the library, node index and step of each) and streams population i
-    into x; the moments of that f(x, t + 1) must equal the library's."""
-    w = wl.bandwidth_headline("fp32" if precision == gmf.FP32_SHIFTED else "fp64")
-    b = w.boxes[0]
-    spec = gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed)
+def _sampled_moment_check(ctx, spec, tabs, precision, count, seed):
+    """One library step checked at sampled nodes x: the oracle collides the 27
+    neighbours x - c_i (their populations from the library, with the node
+    index and step of each) and streams population i into x; returns the
+    largest deviation of the library's moments of x from those of that
+    f(x, t + 1), relative to the largest such moment."""
     vel = tabs[0]
-    say(f"moment storage full-size sampled parity {w.name}")
-    with gmf.Context([spec], precision=precision, storage=MOM, tune=1) as ctx:
-        say(f"  config {ctx.config()}")
-        ctx.step(64)
-        t = ctx.t
-        nodes = wl.sample_nodes(spec.n, 100, seed=2)
-        src = np.array([[_neighbour(int(n), -np.asarray(vel[i]), spec) for i in range(27)] for n in nodes])
-        before = ctx.get_nodes(src.ravel()).reshape(len(nodes), 27, 27)
-        ctx.step(1)
-        after = ctx.get_nodes(nodes)
+    t = ctx.t
+    nodes = wl.sample_nodes(spec.n, count, seed=seed)
+    src = np.array([[_neighbour(int(n), -np.asarray(vel[i]), spec) for i in range(27)] for n in nodes])
+    before = ctx.get_nodes(src.ravel()).reshape(len(nodes), 27, 27)
+    ctx.step(1)
+    after = ctx.get_nodes(nodes)
     p = oracle_params(spec, precision=precision)
     worst, scale = 0.0, 0.0
     for j in range(len(nodes)):
         fx = np.array([oracle.collide(before[j, i], p, node=int(src[j, i]), step=t)[i] for i in range(27)])
-        a = raw_moments(after[j], tabs, 1.0, 1)
-        r = raw_moments(fx, tabs, 1.0, 1)
+        a = raw_moments(after[j], tabs, spec.rho0, 1)
+        r = raw_moments(fx, tabs, spec.rho0, 1)
         worst = max(worst, float(np.max(np.abs(a - r))))
         scale = max(scale, float(np.max(np.abs(r))))
-    say(f"  max moment error {worst / scale:.2e}")
-    assert worst / scale < tol
+    return worst / scale
+
+
+@pytest.mark.parametrize("precision,tol", [(gmf.FP32_SHIFTED, 3e-5), (gmf.FP64, 1e-12)])
+def test_full_size_sampled_nodes_vs_oracle(tabs, precision, tol):
+    """256^3, tau 0.8, k_BT 1e-4, seed 1, autotuned tiling and graph step loop
+    (the benchmark's configuration): after 64 steps, one more step checked at
+    100 sampled nodes against the oracle's collisions of their neighbours."""
+    w = wl.bandwidth_headline("fp32" if precision == gmf.FP32_SHIFTED else "fp64")
+    b = w.boxes[0]
+    spec = gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed)
+    say(f"moment storage full-size sampled parity {w.name}")
+    with gmf.Context([spec], precision=precision, storage=MOM, tune=1) as ctx:
+        say(f"  config {ctx.config()}")
+        ctx.step(64)
+        err = _sampled_moment_check(ctx, spec, tabs, precision, 100, seed=2)
+    say(f"  max moment error {err:.2e}")
+    assert err < tol
+
+
+def test_largest_box_1024cube_with_sampling(tabs):
+    """1024^3 (1.07e9 nodes; two 43 GB moment buffers and 26 GB of sampled
+    fields), FP32, sampled every 2 steps: every offset past 2^32 bytes in the
+    tile kernel and the host-interface kernels; sampled nodes match the
+    oracle's collisions; mass and momentum are conserved; the sampled density
+    variance is positive and finite after the first steps from rest."""
+    spec = gmf.ReplicaSpec(1024, 1024, 1024, 1.0, 0.8, 1e-4, 3)
+    say("1024^3 moment storage FP32 with sampling")
+    with gmf.Context([spec], precision=gmf.FP32_SHIFTED, sample_every=2, storage=MOM) as ctx:
+        s0 = ctx.stats()
+        ctx.step(5)
+        err = _sampled_moment_check(ctx, spec, tabs, gmf.FP32_SHIFTED, 60, seed=4)
+        s1 = ctx.stats()
+    say(f"  max moment error {err:.2e}")
+    assert err < 3e-5, err
+    assert abs(s1["mass"] - s0["mass"]) < 1e-6 * s0["mass"]
+    assert np.all(np.abs(s1["momentum"]) < 1e-6 * s0["mass"])
+    assert s1["nsamples"] == 3 and np.isfinite(s1["sum_var"]).all() and s1["sum_var"][0] > 0
 
 
 def test_moment_storage_option_errors():

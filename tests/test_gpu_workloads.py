@@ -236,9 +236,11 @@ def test_largest_box_1024cube_aa_with_sampling(tabs):
 
 
 @pytest.mark.slow
-def test_spectral_equilibration_256cube():
+@pytest.mark.parametrize("storage", [gmf.STORE_POPULATIONS, gmf.STORE_MOMENTS])
+def test_spectral_equilibration_256cube(storage):
     """The Results-section measurement on the headline lattice: 256^3, k_BT 1e-4,
-    GMF-FLBM in FP32, tau in {0.6, 1, 5} batched in one context, 8000 warm-up
+    GMF-FLBM in FP32 (population and moment storage), tau in {0.6, 1, 5}
+    batched in one context, 8000 warm-up
     steps, then 10000 steps with the full-box spectra sampled every 10.  The
     spectral ER_m(|k|) = S_m(|k|) / S_m^theory over the shells |k| = 4..64
     (integer |n|): its mean over the shells is within 1% of 1, and its mean over
@@ -255,8 +257,8 @@ def test_spectral_equilibration_256cube():
     specs = [gmf.ReplicaSpec(256, 256, 256, 1.0, t, kbt, 11 + i) for i, t in enumerate(taus)]
     flat = np.array([kbt / CS2, kbt, 3 * kbt, 5 * kbt, kbt])[:, None]
     names = ("rho", "j", "jsum", "pdiag", "poff")
-    say("spectral ER at 256^3")
-    with gmf.Context(specs, precision=gmf.FP32_SHIFTED, sample_every=10, spectrum=1) as ctx:
+    say(f"spectral ER at 256^3, storage {storage}")
+    with gmf.Context(specs, precision=gmf.FP32_SHIFTED, sample_every=10, spectrum=1, storage=storage) as ctx:
         ctx.step(8000)
         ctx.reset_stats()
         ctx.step(10000)
