@@ -15,12 +15,14 @@
 //
 // Kernel: a workgroup owns a TX x TY x TZ tile and marches through it in z.
 // For each source plane s it runs the collision of every column of the tile
-// plus a one-node halo in x and y ((TX+2)(TY+2) columns, one per thread) and
-// keeps the 27 post-collision populations in LDS; then each tile column adds
-// the 27 populations that stream into it to the moment accumulators of the
-// planes s-1, s, s+1 (by c_z), and writes plane s-1, now complete.  The
-// planes z0-1 and z0+TZ are computed as halo.  The next plane's moments are
-// loaded while the current one is processed.
+// plus a one-node halo in x and y ((TX+2)(TY+2) columns, one per thread, or
+// two rounds of columns per thread for the largest tile) and keeps the 27
+// post-collision populations in LDS; then each tile column adds the 27
+// populations that stream into it to the moment accumulators of the planes
+// s-1, s, s+1 (by c_z), and writes plane s-1, now complete.  The planes z0-1
+// and z0+TZ are computed as halo.  The next plane's moments are loaded while
+// the current one is processed, and where two LDS buffers fit, consecutive
+// planes alternate between them so that one barrier per plane suffices.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
