@@ -16,6 +16,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -39,10 +40,16 @@ VALU_PEAK = 256 * 4 * 2.4e9 / 4 / 1e9   # wave64 VALU instructions per ns: 256 C
 
 
 def kernel_source_hash(kernel: str = "step") -> str:
+    """Hash of the kernel's sources without comments and blank lines, so that
+    an edit of the documentation does not retire a counter profile."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[kernel]:
-        with open(os.path.join(ROOT, "paper_2601_03806_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2601_03806_amd", "csrc", f)) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].strip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 
