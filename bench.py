@@ -165,6 +165,8 @@ def run_gpu(args, torch, gmf, wl):
                 sec = time_context(ctx, stream, st, 4, torch)
                 out[key] = {"seconds": sec, "nodes": spec.n, "steps": st, "config": ctx.config()}
             torch.cuda.synchronize()
+        print("[bench] variance accuracy: 64^3 tau sweep, FP32 batched vs FP64", file=sys.stderr, flush=True)
+        out["variance_accuracy"] = variance_accuracy(torch, gmf, wl, stream)
         # 512^3 precision-stress box, both precisions
         wp = wl.precision_stress("fp32")
         bp = wp.boxes[0]
@@ -176,6 +178,41 @@ def run_gpu(args, torch, gmf, wl):
                 out[key] = {"seconds": sec, "nodes": sp.n, "steps": st, "config": ctx.config()}
             torch.cuda.synchronize()
     return out
+
+
+def variance_accuracy(torch, gmf, wl, stream):
+    """The accuracy half of the metric, outside the timed region: the 64^3 tau
+    sweep (tau 0.51, 0.6, 1, 2, 5, k_B T 1e-4, one batched context per
+    precision, same seeds so the noise is paired), 2000 warm-up + 20000 steps
+    sampled every 10. Reports FP32-shifted over FP64-plain variance ratios of
+    the ten sampled observables and both precisions' ratios to the
+    equilibrium values (rho0 k_BT / cs2 for drho, rho0 k_BT for j and u,
+    3 rho0 k_BT for sum j, 5 rho0 k_BT for sum Pi_aa, rho0 k_BT for
+    sum_{a<b} Pi_ab; times 1 - 1/N for a spatial variance)."""
+    import numpy as np
+    w = wl.tau_sweep("fp32")
+    specs = [gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed) for b in w.boxes]
+    kbt, n = w.boxes[0].kbt, specs[0].n
+    theory = np.array([3 * kbt, kbt, kbt, kbt, 3 * kbt, 5 * kbt, kbt, kbt, kbt, kbt]) * (1 - 1.0 / n)
+    var = {}
+    t0 = time.perf_counter()
+    for prec in (gmf.FP32_SHIFTED, gmf.FP64):
+        with gmf.Context(specs, precision=prec, sample_every=w.sample_every, stream=stream) as ctx:
+            ctx.step(w.warmup)
+            ctx.reset_stats()
+            ctx.step(w.steps)
+            st = [ctx.stats(r) for r in range(len(specs))]
+        var[prec] = np.array([s["sum_var"] / s["nsamples"] for s in st])
+    torch.cuda.synchronize()
+    ratio = var[gmf.FP32_SHIFTED] / var[gmf.FP64]
+    er32, er64 = var[gmf.FP32_SHIFTED] / theory, var[gmf.FP64] / theory
+    return {"workload": w.name, "taus": [b.tau for b in w.boxes], "samples": w.steps // w.sample_every,
+            "fp32_over_fp64_variance": {"min": round(float(ratio.min()), 8), "max": round(float(ratio.max()), 8),
+                                        "max_abs_dev": float(f"{float(np.max(np.abs(ratio - 1))):.3e}")},
+            "er_fp64": {"min": round(float(er64.min()), 4), "max": round(float(er64.max()), 4)},
+            "er_fp32": {"min": round(float(er32.min()), 4), "max": round(float(er32.max()), 4)},
+            "er_fp64_tau_ge_0.6": {"min": round(float(er64[1:].min()), 4), "max": round(float(er64[1:].max()), 4)},
+            "seconds": round(time.perf_counter() - t0, 1)}
 
 
 def copy_probe(torch, gmf, gbytes=1.812, reps=20):
@@ -367,6 +404,8 @@ def main():
                     "achieved": None if valu is None else round(valu / ns, 1),
                     "frac": None if valu is None else round(valu / ns / VALU_PEAK, 4),
                     "traffic": profiled("mstep_fp32_256", r["nodes"], r["config"])}
+    if "variance_accuracy" in res:
+        line["variance_accuracy"] = res["variance_accuracy"]
     if not args.no_cpu and int(os.environ.get("RANK", 0)) == 0:
         print("[bench] oracle timing on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline()
