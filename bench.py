@@ -281,8 +281,8 @@ def main():
                     help="only time a plain device copy of one population buffer (bandwidth reference)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (replicas and slabs would shard "
-              "over GPUs by independent contexts; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (replicas and z slabs would "
+              "shard over GPUs as independent contexts). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -1,9 +1,11 @@
 """Pins of the oracle's noise generator.
 
 Philox4x32-10 is checked against an independent pure-Python implementation of
-the SC'11 description (Salmon, Moraes, Dror, Shaw) and, on the GPU machine, against
-rocRAND run as a black box (tests/test_gpu_rocrand_pin.py).  The Box-Muller
-normals are checked for their distribution.
+the SC'11 description (Salmon, Moraes, Dror, Shaw), the counter and key layout
+against its definition, and the words for uniformity.  The Box-Muller normals
+are checked for their distribution and against the transform written out from
+the words.  (The device generator is checked word for word against the oracle
+in the GPU tests.)
 """
 import numpy as np
 import pytest
