@@ -12,7 +12,7 @@
  * Arithmetic is IEEE double, built with -O2 -ffp-contract=off (no FMA
  * contraction), so each expression rounds exactly as written.
  *
- * Conventions the paper leaves open (each is also listed in the design notes):
+ * Conventions the paper leaves open (the GPU library takes the same ones):
  *   - velocity order inside each Table I group: rest; the six faces
  *     (+x,-x,+y,-y,+z,-z); the twelve edges and then the eight corners, each in
  *     lexicographic order of (cx,cy,cz) with -1 < 0 < +1;

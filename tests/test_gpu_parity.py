@@ -1,6 +1,6 @@
 """GPU parity of the fused stream+collide step against the FP64 oracle.
 
-Tolerances (derivation in the design notes):
+Tolerances:
   FP64: 1e-11 relative on g = f - w rho0 after 200 steps (the two sides differ
         only in rounding order and in last-ulp libm differences of the normals);
   FP32 shifted: 2e-5 relative on g per 100 steps (binary32 rounding of O(1e-2)
