@@ -261,10 +261,16 @@ def cpu_baseline(target_seconds=12.0):
     oracle.set_threads(1)
     glups1, steps1, dt1 = rate(target_seconds / 3)
     oracle.set_threads(threads)
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": glups, "unit": "GLUPS", "cores": threads, "kind": "oracle",
             "sample": f"16^3 FP64 GMF-FLBM (tau=1, kbt=1e-4, seed 1), {steps} steps ({dt:.1f} s) on {threads} threads; "
                       f"single thread {glups1:.3g} GLUPS ({steps1} steps, {dt1:.1f} s)",
-            "value_single_thread": glups1}
+            "value_single_thread": glups1, "cpu": cpu, "host_cpus": os.cpu_count()}
 
 
 def main():
