@@ -1,7 +1,6 @@
 import os
 import sys
 
-import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
@@ -13,4 +12,4 @@ if HERE not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library through its C ABI)")
-    config.addinivalue_line("markers", "slow: longer CPU statistics (still part of the default run)")
+    config.addinivalue_line("markers", "slow: longer statistics runs (still part of the default run)")

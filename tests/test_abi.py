@@ -4,7 +4,6 @@ import ctypes
 import os
 import re
 
-import pytest
 
 import paper_2601_03806_amd as gmf
 

@@ -13,7 +13,6 @@ Tolerances: FP64 1e-11 relative to the largest moment (rounding order only);
 FP32 3e-5 per 100 steps (binary32 rounding of the stored moments and the
 hardware transcendentals of the normals, as for FP32 populations).
 """
-import os
 
 import numpy as np
 import pytest
