@@ -8,10 +8,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <new>
 #include <string>
@@ -501,134 +503,160 @@ int init_state(gmf_ctx* ctx)
     return GMF_OK;
 }
 
-// Time every fitting (streaming pattern, addressing mode, nodes per thread,
-// workgroup-to-XCD mapping) combination on the initial state, keep the
-// fastest, and restore the initial state in the chosen layout.  A/B re-runs the same step from the same source buffer;
-// AA alternates its two step kinds in place (the state then changes, which
-// does not matter for the timing and is undone by the re-initialisation).
-// AA is a candidate only when the options leave the pattern open; A/B only
-// when the workspace has its second buffer.  Results are cached in the file
-// named by GMF_TUNE_CACHE.
+// Autotuner support shared by both storages.  A candidate is up to four
+// integer parameters.  The file named by GMF_TUNE_CACHE caches choices as
+// lines "key v0 v1 v2 v3"; the last line for a key whose parameters still
+// fit the context is used.
+using TuneParams = std::array<int, 4>;
+
+bool tune_cache_read(const std::string& key, const std::function<bool(const TuneParams&)>& valid, TuneParams* out)
+{
+    const char* path = getenv("GMF_TUNE_CACHE");
+    FILE* fh = path ? fopen(path, "r") : nullptr;
+    if (!fh) return false;
+    char k[4096];
+    TuneParams v;
+    bool found = false;
+    while (fscanf(fh, "%4095s %d %d %d %d", k, &v[0], &v[1], &v[2], &v[3]) == 5)
+        if (key == k && valid(v)) {
+            *out = v;
+            found = true;
+        }
+    fclose(fh);
+    return found;
+}
+
+void tune_cache_append(const std::string& key, const TuneParams& v)
+{
+    const char* path = getenv("GMF_TUNE_CACHE");
+    if (FILE* fh = path ? fopen(path, "a") : nullptr) {
+        fprintf(fh, "%s %d %d %d %d\n", key.c_str(), v[0], v[1], v[2], v[3]);
+        fclose(fh);
+    }
+}
+
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~EventPair()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
+// Time every candidate on the context's stream in two rounds, so that a
+// transient slowdown does not decide the choice (the faster round counts):
+// `configure` sets the context up for a candidate, `launch(c, i)` enqueues its
+// step number i; two steps warm up, eight are timed (an even count, so that
+// AA runs whole pull/local pairs).  *best receives the fastest candidate.
+int tune_time(gmf_ctx* ctx, const std::vector<TuneParams>& cands, const std::function<int(const TuneParams&)>& configure,
+              const std::function<hipError_t(const TuneParams&, int)>& launch, TuneParams* best)
+{
+    if (cands.empty()) return GMF_OK;
+    EventPair ev;
+    CK(hipEventCreate(&ev.e0));
+    CK(hipEventCreate(&ev.e1));
+    std::vector<float> ms(cands.size(), 1e30f);
+    const int reps = 8;
+    for (int round = 0; round < 2; ++round)
+        for (size_t c = 0; c < cands.size(); ++c) {
+            const int rc = configure(cands[c]);
+            if (rc != GMF_OK) return rc;
+            CK(launch(cands[c], 0));
+            CK(launch(cands[c], 1));
+            CK(hipEventRecord(ev.e0, ctx->stream));
+            for (int i = 0; i < reps; ++i) CK(launch(cands[c], i));
+            CK(hipEventRecord(ev.e1, ctx->stream));
+            CK(hipEventSynchronize(ev.e1));
+            float t = 0.f;
+            CK(hipEventElapsedTime(&t, ev.e0, ev.e1));
+            ms[c] = std::min(ms[c], t);
+        }
+    *best = cands[std::min_element(ms.begin(), ms.end()) - ms.begin()];
+    return GMF_OK;
+}
+
+std::string boxes_key(const gmf_ctx* ctx)
+{
+    std::string key;
+    for (auto& r : ctx->reps) key += "_" + std::to_string(r.nx) + "x" + std::to_string(r.ny) + "x" + std::to_string(r.nz);
+    return key;
+}
+
+bool contains(const std::vector<int>& v, int x) { return std::find(v.begin(), v.end(), x) != v.end(); }
+
+// Population storage: time every fitting (addressing mode, nodes per thread,
+// streaming pattern, workgroup-to-XCD mapping) combination on the initial
+// state, keep the fastest, and restore the initial state in the chosen
+// layout.  A/B re-runs the same step from the same source buffer; AA
+// alternates its two step kinds in place (the state then changes, which does
+// not matter for the timing and is undone by the re-initialisation).  AA is a
+// candidate only when the options leave the pattern open; A/B only when the
+// workspace has its second buffer.
 int autotune(gmf_ctx* ctx)
 {
-    const char* cache = getenv("GMF_TUNE_CACHE");
     const uint64_t es = ctx->opt.precision == GMF_FP32_SHIFTED ? 4 : 8;
     std::vector<int> patterns;
     if (ctx->opt.streaming != GMF_STREAM_AA) patterns.push_back(GMF_STREAM_AB);
     if (ctx->opt.streaming != GMF_STREAM_AB) patterns.push_back(GMF_STREAM_AA);
-    std::string key = "v3p" + std::to_string(ctx->opt.precision) + "c" + std::to_string(ctx->opt.collision) + "s" +
-                      std::to_string(ctx->opt.streaming);
-    for (auto& r : ctx->reps) key += "_" + std::to_string(r.nx) + "x" + std::to_string(r.ny) + "x" + std::to_string(r.nz);
+    const std::string key = "v3p" + std::to_string(ctx->opt.precision) + "c" + std::to_string(ctx->opt.collision) +
+                            "s" + std::to_string(ctx->opt.streaming) + boxes_key(ctx);
     std::vector<int> maps = {0};
     if (ctx->xcd_count > 1)
         for (int xm = 1; xm < kXcdMaps; ++xm) maps.push_back(xm);
-    int best_mode = ctx->mode, best_npt = ctx->npt, best_pat = ctx->aa ? GMF_STREAM_AA : GMF_STREAM_AB;
-    int best_map = ctx->xcd_map;
-    bool cached = false;
-    if (cache) {
-        if (FILE* fh = fopen(cache, "r")) {
-            char k[4096];
-            int m, v, sp, xm;
-            while (fscanf(fh, "%4095s %d %d %d %d", k, &m, &v, &sp, &xm) == 5)
-                if (key == k && mode_fits(ctx->reps.data(), ctx->nrep, es, m, v) && (v == 1 || v == 2) &&
-                    std::find(patterns.begin(), patterns.end(), sp) != patterns.end() &&
-                    std::find(maps.begin(), maps.end(), xm) != maps.end()) {
-                    best_mode = m;
-                    best_npt = v;
-                    best_pat = sp;
-                    best_map = xm;
-                    cached = true;
-                }
-            fclose(fh);
-        }
-    }
-    if (!cached) {
-        hipEvent_t e0, e1;
-        CK(hipEventCreate(&e0));
-        CK(hipEventCreate(&e1));
-        // every candidate is timed in two rounds (its faster one counts), so
-        // that a transient slowdown does not decide the choice
-        struct Cand {
-            int pat, m, c, xm;
-            float ms;
-        };
-        std::vector<Cand> cands;
+    // parameters: addressing mode, nodes per thread, streaming pattern, mapping
+    auto fits = [&](const TuneParams& v) {
+        return contains({27, 0, 3, 1}, v[0]) && (v[1] == 1 || v[1] == 2) &&
+               mode_fits(ctx->reps.data(), ctx->nrep, es, v[0], v[1]) && contains(patterns, v[2]) &&
+               contains(maps, v[3]);
+    };
+    TuneParams best = {ctx->mode, ctx->npt, ctx->aa ? GMF_STREAM_AA : GMF_STREAM_AB, ctx->xcd_map};
+    if (!tune_cache_read(key, fits, &best)) {
+        std::vector<TuneParams> cands;
         for (int pat : patterns)
             for (int m : {27, 0, 3, 1})
                 for (int c : {1, 2})
                     for (int xm : maps)
-                        if (mode_fits(ctx->reps.data(), ctx->nrep, es, m, c)) cands.push_back({pat, m, c, xm, 1e30f});
-        const int reps = 8;   // even: AA runs whole pull/local pairs
-        for (int round = 0; round < 2; ++round) {
-            for (Cand& cd : cands) {
-                set_layout(ctx, cd.m);
-                int rc = build_grid(ctx, cd.c);
-                if (rc != GMF_OK) return rc;
-                const bool aa = cd.pat == GMF_STREAM_AA;
-                StepArgs a;
-                a.src = ctx->pop(0);
-                a.dst = ctx->pop(aa ? 0 : 1);
-                a.reps = ctx->d_reps();
-                a.blk2rep = ctx->d_blk2rep();
-                a.d_step = nullptr;
-                a.step_base = ctx->step;
-                a.fields = nullptr;
-                a.partials = nullptr;
-                a.nblocks = ctx->nblocks;
-                a.xcd = cd.xm ? ctx->xcd_count : 0u;
-                a.chunk = kXcdChunks[cd.xm];
-                a.tz = 0;
-                auto launch = [&](int i) {
-                    const int sm = aa ? ((i & 1) ? kAALocal : kAAPull) : kAB;
-                    return launch_step(ctx->opt.precision, ctx->opt.collision, false, sm, cd.m, cd.c, a, ctx->nblocks,
-                                       ctx->stream);
-                };
-                CK(launch(0));
-                CK(launch(1));
-                CK(hipEventRecord(e0, ctx->stream));
-                for (int i = 0; i < reps; ++i) CK(launch(i));
-                CK(hipEventRecord(e1, ctx->stream));
-                CK(hipEventSynchronize(e1));
-                float ms = 0.f;
-                CK(hipEventElapsedTime(&ms, e0, e1));
-                cd.ms = std::min(cd.ms, ms);
-            }
-        }
-        float best_ms = 1e30f;
-        for (const Cand& cd : cands)
-            if (cd.ms < best_ms) {
-                best_ms = cd.ms;
-                best_mode = cd.m;
-                best_npt = cd.c;
-                best_pat = cd.pat;
-                best_map = cd.xm;
-            }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        if (cache) {
-            if (FILE* fh = fopen(cache, "a")) {
-                fprintf(fh, "%s %d %d %d %d\n", key.c_str(), best_mode, best_npt, best_pat, best_map);
-                fclose(fh);
-            }
-        }
+                        if (fits({m, c, pat, xm})) cands.push_back({m, c, pat, xm});
+        StepArgs a;
+        auto configure = [&](const TuneParams& v) {
+            set_layout(ctx, v[0]);
+            const int rc = build_grid(ctx, v[1]);
+            std::memset(&a, 0, sizeof(a));
+            a.src = ctx->pop(0);
+            a.dst = ctx->pop(v[2] == GMF_STREAM_AA ? 0 : 1);
+            a.reps = ctx->d_reps();
+            a.blk2rep = ctx->d_blk2rep();
+            a.step_base = ctx->step;
+            a.nblocks = ctx->nblocks;
+            a.xcd = v[3] ? ctx->xcd_count : 0u;
+            a.chunk = kXcdChunks[v[3]];
+            return rc;
+        };
+        auto launch = [&](const TuneParams& v, int i) {
+            const int sm = v[2] == GMF_STREAM_AA ? ((i & 1) ? kAALocal : kAAPull) : kAB;
+            return launch_step(ctx->opt.precision, ctx->opt.collision, false, sm, v[0], v[1], a, ctx->nblocks,
+                               ctx->stream);
+        };
+        const int rc = tune_time(ctx, cands, configure, launch, &best);
+        if (rc != GMF_OK) return rc;
+        tune_cache_append(key, best);
     }
-    ctx->aa = best_pat == GMF_STREAM_AA;
-    ctx->xcd_map = best_map;
-    set_layout(ctx, best_mode);
-    int rc = build_grid(ctx, best_npt);
+    ctx->aa = best[2] == GMF_STREAM_AA;
+    ctx->xcd_map = best[3];
+    set_layout(ctx, best[0]);
+    const int rc = build_grid(ctx, best[1]);
     if (rc != GMF_OK) return rc;
     return init_state(ctx);
 }
 
-// Moment storage: time every (tile shape, tile depth, workgroup mapping) on
-// the initial state like autotune() does for populations, keep the fastest,
-// and restore the initial state.  Cache entries share the file and its line
-// format (key and four integers).
+// Moment storage: time every fitting (tile shape, tile depth, workgroup
+// mapping) on the initial state in the same way, keep the fastest, and
+// restore the initial state.
 int autotune_moments(gmf_ctx* ctx)
 {
-    const char* cache = getenv("GMF_TUNE_CACHE");
-    std::string key = "m2p" + std::to_string(ctx->opt.precision);
-    for (auto& r : ctx->reps) key += "_" + std::to_string(r.nx) + "x" + std::to_string(r.ny) + "x" + std::to_string(r.nz);
+    const size_t es = ctx->opt.precision == GMF_FP32_SHIFTED ? 4 : 8;
+    const std::string key = "m2p" + std::to_string(ctx->opt.precision) + boxes_key(ctx);
     // the halo columns a tile reads again are L2 hits only when neighbouring
     // tiles run on the same XCD: with several XCDs only the XCD mappings are
     // tried (the linear one measured 1.66x the algorithmic reads at 256^3)
@@ -637,92 +665,45 @@ int autotune_moments(gmf_ctx* ctx)
         for (int xm = 1; xm < kXcdMaps; ++xm) maps.push_back(xm);
     else
         maps.push_back(0);
-    int best_tile = ctx->mtile, best_map = maps.front();
-    uint32_t best_tz = ctx->mtz;
-    bool cached = false;
-    if (cache) {
-        if (FILE* fh = fopen(cache, "r")) {
-            char k[4096];
-            int tl, tz, xm, unused;
-            while (fscanf(fh, "%4095s %d %d %d %d", k, &tl, &tz, &xm, &unused) == 5)
-                if (key == k && tl >= 0 && tl < kMTiles && tz >= (int)kMTz[0] &&
-                    mtile_fits(tl, ctx->opt.precision == GMF_FP32_SHIFTED ? 4 : 8) &&
-                    std::find(maps.begin(), maps.end(), xm) != maps.end()) {
-                    best_tile = tl;
-                    best_tz = (uint32_t)tz;
-                    best_map = xm;
-                    cached = true;
-                }
-            fclose(fh);
-        }
-    }
-    if (!cached) {
-        hipEvent_t e0, e1;
-        CK(hipEventCreate(&e0));
-        CK(hipEventCreate(&e1));
-        struct Cand {
-            int tile;
-            uint32_t tz;
-            int xm;
-            float ms;
-        };
-        std::vector<Cand> cands;
-        const size_t es = ctx->opt.precision == GMF_FP32_SHIFTED ? 4 : 8;
+    // parameters: tile shape, tile depth, mapping, unused
+    auto fits = [&](const TuneParams& v) {
+        return v[0] >= 0 && v[0] < kMTiles && mtile_fits(v[0], es) && v[1] >= (int)kMTz[0] && contains(maps, v[2]);
+    };
+    TuneParams best = {ctx->mtile, (int)ctx->mtz, maps.front(), 0};
+    if (!tune_cache_read(key, fits, &best)) {
+        std::vector<TuneParams> cands;
         for (int tl = 0; tl < kMTiles; ++tl)
             for (uint32_t tz : kMTz)
                 for (int xm : maps)
-                    if (mtile_fits(tl, es)) cands.push_back({tl, tz, xm, 1e30f});
-        const int reps = 8;
-        for (int round = 0; round < 2; ++round) {
-            for (Cand& cd : cands) {
-                ctx->mtile = cd.tile;
-                ctx->mtz = cd.tz;
-                int rc = build_grid(ctx, 1);
-                if (rc != GMF_OK) return rc;
-                StepArgs a;
-                std::memset(&a, 0, sizeof(a));
-                a.src = ctx->pop(0);
-                a.dst = ctx->pop(1);
-                a.reps = ctx->d_reps();
-                a.blk2rep = ctx->d_blk2rep();
-                a.step_base = ctx->step;
-                a.nblocks = ctx->nblocks;
-                a.xcd = cd.xm ? ctx->xcd_count : 0u;
-                a.chunk = kXcdChunks[cd.xm];
-                a.tz = cd.tz;
-                auto launch = [&]() { return launch_mstep(ctx->opt.precision, false, cd.tile, a, ctx->nblocks, ctx->stream); };
-                CK(launch());
-                CK(launch());
-                CK(hipEventRecord(e0, ctx->stream));
-                for (int i = 0; i < reps; ++i) CK(launch());
-                CK(hipEventRecord(e1, ctx->stream));
-                CK(hipEventSynchronize(e1));
-                float ms = 0.f;
-                CK(hipEventElapsedTime(&ms, e0, e1));
-                cd.ms = std::min(cd.ms, ms);
-            }
-        }
-        float best_ms = 1e30f;
-        for (const Cand& cd : cands)
-            if (cd.ms < best_ms) {
-                best_ms = cd.ms;
-                best_tile = cd.tile;
-                best_tz = cd.tz;
-                best_map = cd.xm;
-            }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        if (cache) {
-            if (FILE* fh = fopen(cache, "a")) {
-                fprintf(fh, "%s %d %u %d 0\n", key.c_str(), best_tile, best_tz, best_map);
-                fclose(fh);
-            }
-        }
+                    if (fits({tl, (int)tz, xm, 0})) cands.push_back({tl, (int)tz, xm, 0});
+        StepArgs a;
+        auto configure = [&](const TuneParams& v) {
+            ctx->mtile = v[0];
+            ctx->mtz = (uint32_t)v[1];
+            const int rc = build_grid(ctx, 1);
+            std::memset(&a, 0, sizeof(a));
+            a.src = ctx->pop(0);
+            a.dst = ctx->pop(1);
+            a.reps = ctx->d_reps();
+            a.blk2rep = ctx->d_blk2rep();
+            a.step_base = ctx->step;
+            a.nblocks = ctx->nblocks;
+            a.xcd = v[2] ? ctx->xcd_count : 0u;
+            a.chunk = kXcdChunks[v[2]];
+            a.tz = (uint32_t)v[1];
+            return rc;
+        };
+        auto launch = [&](const TuneParams& v, int) {
+            return launch_mstep(ctx->opt.precision, false, v[0], a, ctx->nblocks, ctx->stream);
+        };
+        const int rc = tune_time(ctx, cands, configure, launch, &best);
+        if (rc != GMF_OK) return rc;
+        tune_cache_append(key, best);
     }
-    ctx->mtile = best_tile;
-    ctx->mtz = best_tz;
-    ctx->xcd_map = best_map;
-    int rc = build_grid(ctx, 1);
+    ctx->mtile = best[0];
+    ctx->mtz = (uint32_t)best[1];
+    ctx->xcd_map = best[2];
+    const int rc = build_grid(ctx, 1);
     if (rc != GMF_OK) return rc;
     return init_state(ctx);
 }

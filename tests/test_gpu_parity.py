@@ -292,3 +292,26 @@ def test_nan_injection_reports_unstable(w):
         with pytest.raises(gmf.GmfError) as e:
             ctx.stats()
         assert e.value.code == gmf.GMF_EUNSTABLE
+
+
+def test_tune_cache(tmp_path, monkeypatch):
+    """GMF_TUNE_CACHE: an entry whose parameters do not fit is ignored and the
+    tuner appends its choice; a second context with the same boxes takes the
+    cached choice without timing again and reproduces the trajectory bit for
+    bit, for population and moment storage."""
+    cache = tmp_path / "tune.txt"
+    cache.write_text("v3p1c0s0_24x20x18 99 1 1 0\nm2p1_24x20x18 7 64 1 0\n")
+    monkeypatch.setenv("GMF_TUNE_CACHE", str(cache))
+    spec = gmf.ReplicaSpec(24, 20, 18, 1.0, 0.8, 1e-4, 6)
+    for storage in (gmf.STORE_POPULATIONS, gmf.STORE_MOMENTS):
+        say(f"tune cache storage={storage}")
+        runs = []
+        for _ in range(2):
+            before = cache.read_text().splitlines()
+            with gmf.Context([spec], precision=gmf.FP32_SHIFTED, tune=1, storage=storage) as ctx:
+                cfg = ctx.config()
+                ctx.step(10)
+                runs.append((cfg, ctx.get_populations(), len(cache.read_text().splitlines()) - len(before)))
+        assert runs[0][2] == 1 and runs[1][2] == 0, (runs[0][2], runs[1][2])   # timed once, then cached
+        assert runs[0][0] == runs[1][0]
+        assert np.array_equal(runs[0][1], runs[1][1])
