@@ -153,6 +153,11 @@ int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         }
     }
     if (choose_mode(reps, nrep, es, 1) < 0) return GMF_EINVAL;
+    // workgroup and tile counts of the whole context are 32-bit: fewer than
+    // 2^32 nodes in all (far beyond any device memory) keeps every one in range
+    uint64_t total = 0;
+    for (int r = 0; r < nrep; ++r) total += (uint64_t)reps[r].nx * reps[r].ny * reps[r].nz;
+    if (total >= (1ull << 32)) return GMF_EINVAL;
     return GMF_OK;
 }
 

@@ -79,6 +79,9 @@ def test_workspace_bytes_and_validation():
     assert _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], storage=2) == 0
     assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)], storage=gmf.STORE_MOMENTS, sample_every=10,
                spectrum=1) > 2 * 10 * 8 * 512 ** 3
+    # fewer than 2^32 nodes in one context (its 32-bit workgroup counts)
+    assert _ws([(1024, 1024, 1024, 1.0, 1.0, 1e-4, 1)] * 4, precision=gmf.FP32_SHIFTED) == 0
+    assert _ws([(1024, 1024, 1024, 1.0, 1.0, 1e-4, 1)] * 3, precision=gmf.FP32_SHIFTED) > 0
     # the 512^3 stress workload fits both precisions
     assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)]) > 2 * 27 * 8 * 512 ** 3
     assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)], precision=gmf.FP32_SHIFTED) > 0
