@@ -157,7 +157,19 @@ typedef struct {
 } gmf_stats_t;
 
 /* Device bytes gmf_init needs when the caller provides the workspace.
- * Returns 0 when the arguments are invalid. */
+ * Returns 0 when the arguments are invalid.  Size limits (each one an
+ * argument error):
+ *   1 <= nrep <= 65535; fewer than 2^32 nodes over all replicas;
+ *   per replica nx*ny*nz < 2^31 and one z plane of 27 populations
+ *   (nx*ny*27*element bytes) under 4 GiB;
+ *   some addressing mode of the step kernel fits every replica: either a
+ *   storage group of 27, 3 or 1 populations over the whole replica within
+ *   32-bit byte offsets (at the least nx*ny*nz*element bytes < 4 GiB), or
+ *   every z plane a whole number of 256-node workgroups;
+ *   with sampling: at most 2^16 spectrum work chunks per replica (nz planes,
+ *   taken 256/nx at a time when nx <= 256) and sum(6 * 28 * nz) < 2^32 over
+ *   the replicas;
+ *   with full-box spectra: nx, ny, nz <= 1024 with prime factors 2, 3, 5. */
 size_t gmf_workspace_bytes(const gmf_replica* reps, int32_t nrep, const gmf_options* opt);
 
 /* Create a context for nrep replicas and set each to rest equilibrium.

@@ -153,6 +153,17 @@ int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         }
     }
     if (choose_mode(reps, nrep, es, 1) < 0) return GMF_EINVAL;
+    // sampling: the first DFT stage's work list packs (replica, chunk) into 16
+    // bits each, and the plane sums of all replicas sit at 32-bit offsets
+    if (opt && opt->sample_every > 0) {
+        uint64_t dft = 0;
+        for (int r = 0; r < nrep; ++r) {
+            const uint32_t P = dft_planes_per_block((uint32_t)reps[r].nx);
+            if (((uint64_t)reps[r].nz + P - 1) / P > (1ull << 16)) return GMF_EINVAL;
+            dft += (uint64_t)kFields * reps[r].nz * kDftPlane;
+        }
+        if (dft >= (1ull << 32)) return GMF_EINVAL;
+    }
     // workgroup and tile counts of the whole context are 32-bit: fewer than
     // 2^32 nodes in all (far beyond any device memory) keeps every one in range
     uint64_t total = 0;

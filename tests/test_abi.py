@@ -82,6 +82,12 @@ def test_workspace_bytes_and_validation():
     # fewer than 2^32 nodes in one context (its 32-bit workgroup counts)
     assert _ws([(1024, 1024, 1024, 1.0, 1.0, 1e-4, 1)] * 4, precision=gmf.FP32_SHIFTED) == 0
     assert _ws([(1024, 1024, 1024, 1.0, 1.0, 1e-4, 1)] * 3, precision=gmf.FP32_SHIFTED) > 0
+    # sampling: at most 2^16 DFT chunks per replica, 32-bit offsets of the plane sums
+    assert _ws([(512, 1, 65600, 1.0, 1.0, 1e-4, 1)], precision=gmf.FP32_SHIFTED) > 0
+    assert _ws([(512, 1, 65600, 1.0, 1.0, 1e-4, 1)], precision=gmf.FP32_SHIFTED, sample_every=10) == 0
+    assert _ws([(512, 1, 65536, 1.0, 1.0, 1e-4, 1)], precision=gmf.FP32_SHIFTED, sample_every=10) > 0
+    assert _ws([(1, 1, 1 << 24, 1.0, 1.0, 1e-4, 1)], sample_every=10) > 0
+    assert _ws([(1, 1, 1 << 24, 1.0, 1.0, 1e-4, 1)] * 2, sample_every=10) == 0
     # the 512^3 stress workload fits both precisions
     assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)]) > 2 * 27 * 8 * 512 ** 3
     assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)], precision=gmf.FP32_SHIFTED) > 0
