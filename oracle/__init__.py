@@ -82,12 +82,14 @@ def lib():
 
 
 def _dp(a: np.ndarray):
-    assert a.dtype == np.float64 and a.flags.c_contiguous
+    if a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise ValueError("expected a C-contiguous float64 array")
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
 def _u32p(a: np.ndarray):
-    assert a.dtype == np.uint32 and a.flags.c_contiguous
+    if a.dtype != np.uint32 or not a.flags.c_contiguous:
+        raise ValueError("expected a C-contiguous uint32 array")
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
 
 
@@ -134,6 +136,8 @@ def normals(seed: int, node: int, step: int, bits: int = 32) -> np.ndarray:
 
 def feq(rho: float, u) -> np.ndarray:
     uu = np.ascontiguousarray(u, dtype=np.float64)
+    if uu.size != 3:
+        raise ValueError("feq: u needs three components")
     out = np.zeros(Q)
     lib().oracle_feq(rho, _dp(uu), _dp(out))
     return out
@@ -141,6 +145,8 @@ def feq(rho: float, u) -> np.ndarray:
 
 def collide(f, p: Params, node: int = 0, step: int = 0, moment_space: bool = False) -> np.ndarray:
     ff = np.ascontiguousarray(f, dtype=np.float64)
+    if ff.size != Q:
+        raise ValueError("collide: one node's 27 populations")
     out = np.zeros(Q)
     fn = lib().oracle_collide_moment_space if moment_space else lib().oracle_collide
     fn(_dp(ff), ctypes.byref(p), node, step, _dp(out))
@@ -153,9 +159,14 @@ def rest_state(p: Params) -> np.ndarray:
     return f
 
 
+def _check_pops(p: Params, f: np.ndarray):
+    if f.shape != (Q * p.nx * p.ny * p.nz,):
+        raise ValueError(f"populations of shape {f.shape} for a {p.nx}x{p.ny}x{p.nz} box")
+
+
 def run(p: Params, f: np.ndarray, t0: int, nsteps: int) -> np.ndarray:
     """Advance the canonical populations f (27*N, f[i*N+n]) in place."""
-    assert f.shape == (Q * p.nx * p.ny * p.nz,)
+    _check_pops(p, f)
     rc = lib().oracle_run(ctypes.byref(p), _dp(f), t0, nsteps)
     if rc != 0:
         raise ValueError(f"oracle_run failed with {rc}")
@@ -163,6 +174,7 @@ def run(p: Params, f: np.ndarray, t0: int, nsteps: int) -> np.ndarray:
 
 
 def moments(p: Params, f: np.ndarray):
+    _check_pops(p, f)
     N = p.nx * p.ny * p.nz
     rho = np.zeros(N)
     u = np.zeros(3 * N)
@@ -171,6 +183,7 @@ def moments(p: Params, f: np.ndarray):
 
 
 def totals(p: Params, f: np.ndarray) -> np.ndarray:
+    _check_pops(p, f)
     out = np.zeros(4)
     lib().oracle_totals(ctypes.byref(p), _dp(f), _dp(out))
     return out
@@ -178,6 +191,7 @@ def totals(p: Params, f: np.ndarray) -> np.ndarray:
 
 def observables(p: Params, f: np.ndarray):
     """(sums[NOBS,2], spectra[NSPEC,NSHELL]) of one state; see gmf_oracle.c."""
+    _check_pops(p, f)
     sums = np.zeros(2 * NOBS)
     spec = np.zeros(NSPEC * NSHELL)
     lib().oracle_observables(ctypes.byref(p), _dp(f), _dp(sums), _dp(spec))

@@ -131,7 +131,8 @@ def _check(rc: int, where: str):
 
 
 def _dp(a: np.ndarray):
-    assert a.dtype == np.float64 and a.flags.c_contiguous
+    if a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise ValueError("expected a C-contiguous float64 array")
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
@@ -311,11 +312,12 @@ class Context:
 
     def set_populations(self, f: np.ndarray, r: int = 0):
         ff = np.ascontiguousarray(f, dtype=np.float64)
-        assert ff.size == Q * self.specs[r].n
+        if ff.size != Q * self.specs[r].n:
+            raise ValueError(f"set_populations: {ff.size} values for a replica of {self.specs[r].n} nodes x {Q}")
         _check(lib().gmf_set_populations(self._h, r, _dp(ff)), "gmf_set_populations")
 
     def get_nodes(self, nodes, r: int = 0) -> np.ndarray:
-        nd = np.ascontiguousarray(nodes, dtype=np.int64)
+        nd = np.ascontiguousarray(nodes, dtype=np.int64).ravel()
         out = np.zeros((len(nd), Q))
         rc = lib().gmf_get_nodes(self._h, r, nd.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(nd), _dp(out))
         _check(rc, "gmf_get_nodes")
