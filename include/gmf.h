@@ -38,6 +38,17 @@
  * No C++ exception crosses this interface; every function returns one of the
  * GMF_* codes below.  After a HIP error a context is poisoned: every later
  * call on it returns GMF_EDEVICE.
+ *
+ * Environment variables, read by gmf_init (none changes a trajectory's bits):
+ *   GMF_TUNE_CACHE   file that caches the autotuner's choices (tune = 1),
+ *                    one line per box set and options; appended to
+ *   GMF_ADDRESSING   plane | 27 | 3 | 1: force the population addressing mode
+ *                    (ignored where it does not fit the boxes)
+ *   GMF_BLOCK_MAP    linear | xcd | xcd16: force the workgroup-to-XCD mapping
+ *   GMF_MTILE        "tile,depth": force the moment-storage tiling (tile 0..3
+ *                    = 64x8, 32x16, 32x8, 64x16; depth >= 16 planes)
+ *   GMF_DEBUG        print each failing HIP call to stderr
+ * The autotuner (tune = 1) overrides the forced choices it searches.
  */
 #ifndef GMF_H
 #define GMF_H
