@@ -93,17 +93,18 @@ def time_context(ctx, stream, steps, warmup, torch):
 def run_gpu(args, torch, gmf, wl):
     stream = torch.cuda.Stream()
     out = {}
-    # FP32 shifted, bandwidth headline
-    w = wl.bandwidth_headline("fp32")
+    # bandwidth headline: FP32 shifted (FP64 plain in profiling runs of that kernel)
+    w = wl.bandwidth_headline(args.precision)
     b = w.boxes[0]
     spec = gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed)
     storage = gmf.STORE_MOMENTS if args.storage == "moments" else gmf.STORE_POPULATIONS
-    with gmf.Context([spec], precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune, storage=storage) as ctx:
-        print(f"[bench] fp32 {w.name} ({args.storage}): warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
+    head_prec = gmf.FP64 if args.precision == "fp64" else gmf.FP32_SHIFTED
+    with gmf.Context([spec], precision=head_prec, stream=stream, tune=args.tune, storage=storage) as ctx:
+        print(f"[bench] {w.name} ({args.storage}): warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
               flush=True)
         sec = time_context(ctx, stream, args.steps, args.warmup, torch)
         st = ctx.stats()
-        out["fp32"] = {"seconds": sec, "nodes": spec.n, "steps": args.steps, "config": ctx.config(),
+        out["headline"] = {"seconds": sec, "nodes": spec.n, "steps": args.steps, "config": ctx.config(),
                        "mass_drift_rel": abs(st["mass"] - spec.n * b.rho0) / (spec.n * b.rho0)}
     torch.cuda.synchronize()
     if not args.skip_extra:
@@ -283,9 +284,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--storage", choices=("populations", "moments"), default="populations",
                     help="storage of the FP32 256^3 headline run (moments: profiling of the moment-storage kernel)")
+    ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32",
+                    help="precision of the 256^3 headline run (fp64: profiling of the FP64 kernel, with --skip-extra)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain device copy of one population buffer (bandwidth reference)")
     args = ap.parse_args()
+    if args.precision == "fp64" and not args.skip_extra:
+        ap.error("--precision fp64 profiles the FP64 kernel alone: add --skip-extra")
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (replicas and z slabs would "
               "shard over GPUs as independent contexts). Run with --gpus 1.", file=sys.stderr)
@@ -305,15 +310,15 @@ def main():
         return
 
     res = run_gpu(args, torch, gmf, wl)
-    r32 = res["fp32"]
-    glups = r32["nodes"] * r32["steps"] / r32["seconds"] / 1e9
-    ms = r32["seconds"] / r32["steps"] * 1e3
+    rh = res["headline"]
+    glups = rh["nodes"] * rh["steps"] / rh["seconds"] / 1e9
+    ms = rh["seconds"] / rh["steps"] * 1e3
     # roofline of the step kernel: algorithmic bytes per launch over its average
     # launch duration, i.e. the events around the timed region over its launches
     # (the captured step loop launches the step kernel back to back)
-    kernel_s = r32["seconds"] / r32["steps"]
-    bpn = (MOM_BYTES_PER_NODE if args.storage == "moments" else BYTES_PER_NODE)["fp32"]
-    achieved = bpn * r32["nodes"] / kernel_s / 1e9
+    kernel_s = rh["seconds"] / rh["steps"]
+    bpn = (MOM_BYTES_PER_NODE if args.storage == "moments" else BYTES_PER_NODE)[args.precision]
+    achieved = bpn * rh["nodes"] / kernel_s / 1e9
     line = {
         "metric": METRIC,
         "value": round(glups, 4),
@@ -325,20 +330,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic (equilibrium fluid at rest, rho0=1, Philox noise)",
-        "config": {"workload": "d3q27_256cube_fp32_tau0.8", "lattice": [256, 256, 256], "rho0": 1.0,
-                   "tau": 0.8, "kbt": 1e-4, "seed": 1, "precision": "fp32_shifted",
+        "config": {"workload": f"d3q27_256cube_{args.precision}_tau0.8", "lattice": [256, 256, 256], "rho0": 1.0,
+                   "tau": 0.8, "kbt": 1e-4, "seed": 1,
+                   "precision": "fp64_plain" if args.precision == "fp64" else "fp32_shifted",
                    "layout": ("ten moments per node, A/B" if args.storage == "moments" else
-                              "row-interleaved populations, " + ("in-place AA" if r32["config"]["streaming"] == "AA"
+                              "row-interleaved populations, " + ("in-place AA" if rh["config"]["streaming"] == "AA"
                                                                  else "A/B pull")),
-                   "kernel_config": r32["config"]},
+                   "kernel_config": rh["config"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": profiled("mstep_fp32_256" if args.storage == "moments" else "step_fp32_256",
-                                         r32["nodes"], r32["config"])},
+                     "traffic": profiled(("mstep" if args.storage == "moments" else "step") + f"_{args.precision}_256",
+                                         rh["nodes"], rh["config"])},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
-        "mass_drift_rel": r32["mass_drift_rel"],
+        "mass_drift_rel": rh["mass_drift_rel"],
     }
     if "fp64" in res:
         r = res["fp64"]
@@ -347,6 +353,7 @@ def main():
         line["fp64_plain"] = {"workload": "d3q27_256cube_fp64_tau0.8", "glups": round(g, 4),
                               "ms_per_step": round(r["seconds"] / r["steps"] * 1e3, 5),
                               "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                              "traffic": profiled("step_fp64_256", r["nodes"], r["config"]),
                               "steps": r["steps"], "kernel_config": r["config"]}
     if "batched" in res:
         r = res["batched"]
