@@ -283,42 +283,10 @@ def cpu_baseline(target_seconds=12.0):
             "value_single_thread": glups1, "cpu": cpu, "host_cpus": os.cpu_count()}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--tune", type=int, default=1, help="1: autotune the kernel variant at init (default)")
-    ap.add_argument("--skip-extra", action="store_true", help="only the FP32 headline (profiling runs)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
-    ap.add_argument("--storage", choices=("populations", "moments"), default="populations",
-                    help="storage of the FP32 256^3 headline run (moments: profiling of the moment-storage kernel)")
-    ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32",
-                    help="precision of the 256^3 headline run (fp64: profiling of the FP64 kernel, with --skip-extra)")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="only time a plain device copy of one population buffer (bandwidth reference)")
-    args = ap.parse_args()
-    if args.precision == "fp64" and not args.skip_extra:
-        ap.error("--precision fp64 profiles the FP64 kernel alone: add --skip-extra")
-    if args.gpus != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path (replicas and z slabs would "
-              "shard over GPUs as independent contexts). Run with --gpus 1.", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import paper_2601_03806_amd as gmf
-    from paper_2601_03806_amd import workloads as wl
-
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
-    gmf.lib()   # fail loudly if the HIP library is missing
-    if args.copy_probe:
-        print(json.dumps({"copy_probe": copy_probe(torch, gmf)}), flush=True)
-        return
-
-    res = run_gpu(args, torch, gmf, wl)
+def make_line(args, res) -> dict:
+    """The bench's JSON line (without the oracle timing) from the timed
+    results of run_gpu: the headline figures, its roofline and the extra
+    workloads that ran."""
     rh = res["headline"]
     glups = rh["nodes"] * rh["steps"] / rh["seconds"] / 1e9
     ms = rh["seconds"] / rh["steps"] * 1e3
@@ -428,6 +396,51 @@ def main():
                     "traffic": profiled("mstep_fp32_256", r["nodes"], r["config"])}
     if "variance_accuracy" in res:
         line["variance_accuracy"] = res["variance_accuracy"]
+    return line
+
+
+def parse_args(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--tune", type=int, default=1, help="1: autotune the kernel variant at init (default)")
+    ap.add_argument("--skip-extra", action="store_true", help="only the FP32 headline (profiling runs)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--storage", choices=("populations", "moments"), default="populations",
+                    help="storage of the FP32 256^3 headline run (moments: profiling of the moment-storage kernel)")
+    ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32",
+                    help="precision of the 256^3 headline run (fp64: profiling of the FP64 kernel, with --skip-extra)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only time a plain device copy of one population buffer (bandwidth reference)")
+    args = ap.parse_args(argv)
+    if args.precision == "fp64" and not args.skip_extra:
+        ap.error("--precision fp64 profiles the FP64 kernel alone: add --skip-extra")
+    return args
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the library has no multi-GPU path (replicas and z slabs would "
+              "shard over GPUs as independent contexts). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2601_03806_amd as gmf
+    from paper_2601_03806_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
+    gmf.lib()   # fail loudly if the HIP library is missing
+    if args.copy_probe:
+        print(json.dumps({"copy_probe": copy_probe(torch, gmf)}), flush=True)
+        return
+
+    res = run_gpu(args, torch, gmf, wl)
+    line = make_line(args, res)
     if not args.no_cpu and int(os.environ.get("RANK", 0)) == 0:
         print("[bench] oracle timing on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline()
