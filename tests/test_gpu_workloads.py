@@ -52,15 +52,37 @@ def _sampled_collision_check(ctx, spec, r, tabs, precision, count, seed):
 @pytest.mark.parametrize("precision,tol", [(gmf.FP32_SHIFTED, 2e-5), (gmf.FP64, 1e-12)])
 def test_full_size_sampled_nodes_vs_oracle(tabs, precision, tol):
     """256^3, tau 0.8, k_BT 1e-4, seed 1: the bandwidth workload in its benchmark
-    launch configuration (graph step loop), checked node by node."""
+    launch configuration (autotuned variant, graph step loop), checked node by
+    node."""
     w = wl.bandwidth_headline("fp32" if precision == gmf.FP32_SHIFTED else "fp64")
     b = w.boxes[0]
     spec = gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed)
     say(f"full-size sampled parity {w.name}")
-    with gmf.Context([spec], precision=precision) as ctx:
+    with gmf.Context([spec], precision=precision, tune=1) as ctx:
+        say(f"  config {ctx.config()}")
         ctx.step(64)                                        # one graph replay
         err = _sampled_collision_check(ctx, spec, 0, tabs, precision, 300, seed=1)
+    say(f"  max error {err:.2e}")
     assert err < tol, err
+
+
+def test_ensemble_sampled_nodes_vs_oracle_in_bench_configuration(tabs):
+    """The 64-replica ensemble (32 x 32^3, 16 x 48^3, 16 x 64^3, drawn taus,
+    seeds 1..64, k_BT 1e-4), FP32 shifted, in its benchmark launch
+    configuration (autotuned streaming pattern, addressing and mapping; graph
+    step loop): after 64 steps, one step per checked replica at 100 sampled
+    nodes of the first and last replica of each size against the oracle's
+    collisions (the AA pattern, when chosen, is checked in both states)."""
+    w = wl.ensemble()
+    specs = [gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed) for b in w.boxes]
+    say(f"ensemble sampled parity {w.name}")
+    with gmf.Context(specs, precision=gmf.FP32_SHIFTED, tune=1) as ctx:
+        say(f"  config {ctx.config()}")
+        ctx.step(64)
+        for k, r in enumerate((0, 31, 32, 47, 48, 63)):
+            err = _sampled_collision_check(ctx, specs[r], r, tabs, gmf.FP32_SHIFTED, 100, seed=10 + k)
+            say(f"  replica {r} ({specs[r].nx}^3, tau {specs[r].tau}): max error {err:.2e}")
+            assert err < 2e-5, (r, err)
 
 
 def test_precision_stress_embedded_box_and_large_box(tabs):
