@@ -66,6 +66,23 @@ def test_full_size_sampled_nodes_vs_oracle(tabs, precision, tol):
     assert err < tol, err
 
 
+@pytest.mark.parametrize("precision,tol", [(gmf.FP32_SHIFTED, 2e-5), (gmf.FP64, 1e-12)])
+def test_512cube_sampled_nodes_vs_oracle_in_bench_configuration(tabs, precision, tol):
+    """512^3, tau 0.55, k_BT 1e-5, seed 1, alone in its context as the benchmark
+    runs it (autotuned variant, graph step loop): after 64 steps, one step
+    checked at 200 sampled nodes against the oracle's collisions."""
+    w = wl.precision_stress("fp32" if precision == gmf.FP32_SHIFTED else "fp64")
+    b = w.boxes[0]
+    spec = gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed)
+    say(f"512^3 sampled parity prec={precision}")
+    with gmf.Context([spec], precision=precision, tune=1) as ctx:
+        say(f"  config {ctx.config()}")
+        ctx.step(64)
+        err = _sampled_collision_check(ctx, spec, 0, tabs, precision, 200, seed=5)
+    say(f"  max error {err:.2e}")
+    assert err < tol, err
+
+
 def test_ensemble_sampled_nodes_vs_oracle_in_bench_configuration(tabs):
     """The 64-replica ensemble (32 x 32^3, 16 x 48^3, 16 x 64^3, drawn taus,
     seeds 1..64, k_BT 1e-4), FP32 shifted, in its benchmark launch
