@@ -18,20 +18,26 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    """Compile every source (in parallel, one hipcc per file) and link libgmf.so."""
+    jobs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         cmd = ["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
+        jobs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    objs, failed = [], []
+    for src, obj, proc in jobs:
+        _, stderr = proc.communicate()
         # the host pass does not know the packed-fp32 feature; that warning is harmless
-        err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
-        if r.returncode != 0:
-            raise RuntimeError(f"hipcc failed for {src}:\n{err}")
-        if err.strip() and verbose:
+        err = "\n".join(l for l in stderr.splitlines() if "packed-fp32-ops" not in l)
+        if proc.returncode != 0:
+            failed.append(f"hipcc failed for {src}:\n{err}")
+        elif err.strip() and verbose:
             print(err, file=sys.stderr)
         objs.append(obj)
+    if failed:
+        raise RuntimeError("\n".join(failed))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     if verbose:
