@@ -249,27 +249,29 @@ def copy_probe(torch, gmf, gbytes=1.812, reps=20):
 
 
 def cpu_baseline(target_seconds=12.0):
-    """The FP64 oracle as written, on the host: OpenMP over z planes on every
-    thread it gets (the reported value), then the same on one thread."""
+    """The FP64 oracle as written, on the host, on a bounded sample of the
+    headline workload itself (the 256^3 box, tau 0.8, k_B T 1e-4, seed 1, from
+    rest): OpenMP over z planes on every thread it gets, as many whole steps as
+    fit in about target_seconds (the reported value); then one thread on a 64^3
+    box with the same parameters."""
     import oracle
-    L = 16
-    p = oracle.params(L, rho0=1.0, tau=1.0, kbt=1e-4, seed=1)
 
-    def rate(seconds):
+    def rate(L, seconds):
+        p = oracle.params(L, rho0=1.0, tau=0.8, kbt=1e-4, seed=1)
         f = oracle.rest_state(p)
         t0 = time.perf_counter()
-        oracle.run(p, f, 0, 5)
+        oracle.run(p, f, 0, 1)                       # sizes the run
         dt = time.perf_counter() - t0
-        steps = max(5, int(seconds / max(dt / 5, 1e-6)))
+        steps = max(1, int(seconds / max(dt, 1e-6)))
         t0 = time.perf_counter()
-        oracle.run(p, f, 5, steps)
+        oracle.run(p, f, 1, steps)
         dt = time.perf_counter() - t0
         return L ** 3 * steps / dt / 1e9, steps, dt
 
     threads = oracle.num_threads()
-    glups, steps, dt = rate(target_seconds)
+    glups, steps, dt = rate(256, target_seconds)
     oracle.set_threads(1)
-    glups1, steps1, dt1 = rate(target_seconds / 3)
+    glups1, steps1, dt1 = rate(64, target_seconds / 3)
     oracle.set_threads(threads)
     cpu = "unknown CPU"
     try:
@@ -278,8 +280,9 @@ def cpu_baseline(target_seconds=12.0):
     except (OSError, StopIteration):
         pass
     return {"value": glups, "unit": "GLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"16^3 FP64 GMF-FLBM (tau=1, kbt=1e-4, seed 1), {steps} steps ({dt:.1f} s) on {threads} threads; "
-                      f"single thread {glups1:.3g} GLUPS ({steps1} steps, {dt1:.1f} s)",
+            "sample": f"256^3 FP64 GMF-FLBM (the headline box: tau=0.8, kbt=1e-4, seed 1, from rest), {steps} step{'s' * (steps != 1)} "
+                      f"({dt:.1f} s) on {threads} threads; single thread on 64^3 with the same parameters "
+                      f"{glups1:.3g} GLUPS ({steps1} step{'s' * (steps1 != 1)}, {dt1:.1f} s)",
             "value_single_thread": glups1, "cpu": cpu, "host_cpus": os.cpu_count()}
 
 
