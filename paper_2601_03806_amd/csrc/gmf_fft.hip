@@ -98,9 +98,12 @@ __device__ __forceinline__ void small_dft<5>(double2 (&v)[5])
 
 // One stage over W lines of length L (rows of `ld` values in buf).  twl[m] =
 // e^{+2 pi i m / L}.  Every thread reads all its butterflies before the
-// barrier and writes them after it, so the stage works in place.
-template <int R>
-__device__ __forceinline__ void fft_stage(double2* buf, const double2* twl, uint32_t L, uint32_t W, uint32_t ld, uint32_t Ns)
+// barrier and writes them after it, so the stage works in place.  P2: L is a
+// power of two (then so are L / R and Ns, and the index arithmetic is shifts
+// and masks; lnb = log2(L / R)).
+template <int R, bool P2>
+__device__ __forceinline__ void fft_stage(double2* buf, const double2* twl, uint32_t L, uint32_t W, uint32_t ld,
+                                          uint32_t Ns, uint32_t lnb)
 {
     constexpr uint32_t kMaxB = (kFftPoints / R + kBlock - 1) / kBlock;
     const uint32_t nb = L / R, total = W * nb, span = L / (Ns * (uint32_t)R);
@@ -111,15 +114,16 @@ __device__ __forceinline__ void fft_stage(double2* buf, const double2* twl, uint
         const uint32_t b = threadIdx.x + q * kBlock;
         dst[q] = 0;
         if (b < total) {
-            const uint32_t w = b / nb, j = b - w * nb;
-            const uint32_t k = j % Ns;
+            const uint32_t w = P2 ? b >> lnb : b / nb;
+            const uint32_t j = b - w * nb;
+            const uint32_t k = P2 ? j & (Ns - 1) : j % Ns;
             const double2* line = buf + w * ld;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const double2 a = line[j + (uint32_t)r * nb];
                 v[q][r] = r == 0 ? a : cmulc(a, twl[k * (uint32_t)r * span]);
             }
-            dst[q] = w * ld + (j / Ns) * Ns * (uint32_t)R + k;
+            dst[q] = w * ld + (j - k) * (uint32_t)R + k;   // (j / Ns) Ns R + k
         }
     }
     __syncthreads();
@@ -135,6 +139,7 @@ __device__ __forceinline__ void fft_stage(double2* buf, const double2* twl, uint
     __syncthreads();
 }
 
+template <bool P2>
 __device__ __forceinline__ void fft_lines(double2* buf, const double2* twl, uint32_t L, uint32_t W, uint32_t ld)
 {
     // the stages of fft_plan, taken from the part of L not yet transformed (no
@@ -142,11 +147,17 @@ __device__ __forceinline__ void fft_lines(double2* buf, const double2* twl, uint
     uint32_t Ns = 1, m = L;
     while (m > 1) {
         const uint32_t R = m % 4 == 0 ? 4u : (m % 2 == 0 ? 2u : (m % 3 == 0 ? 3u : 5u));
-        switch (R) {
-        case 4: fft_stage<4>(buf, twl, L, W, ld, Ns); break;
-        case 2: fft_stage<2>(buf, twl, L, W, ld, Ns); break;
-        case 3: fft_stage<3>(buf, twl, L, W, ld, Ns); break;
-        default: fft_stage<5>(buf, twl, L, W, ld, Ns); break;
+        const uint32_t lnb = P2 ? (uint32_t)__builtin_ctz(L / R) : 0u;
+        if (P2) {
+            if (R == 4) fft_stage<4, true>(buf, twl, L, W, ld, Ns, lnb);
+            else fft_stage<2, true>(buf, twl, L, W, ld, Ns, lnb);
+        } else {
+            switch (R) {
+            case 4: fft_stage<4, false>(buf, twl, L, W, ld, Ns, 0); break;
+            case 2: fft_stage<2, false>(buf, twl, L, W, ld, Ns, 0); break;
+            case 3: fft_stage<3, false>(buf, twl, L, W, ld, Ns, 0); break;
+            default: fft_stage<5, false>(buf, twl, L, W, ld, Ns, 0); break;
+            }
         }
         Ns *= R;
         m /= R;
@@ -165,22 +176,18 @@ __device__ __forceinline__ int replica_of_block(const uint32_t* first, int32_t n
     return lo;
 }
 
-// One pass of the 3D transform along AXIS for packed array blockIdx.y.
-// AXIS 0 builds the packed values from the sampled fields.
-template <typename T, int AXIS>
-__global__ __launch_bounds__(kBlock) void fft_pass_kernel(const RepDev* reps, const uint32_t* first, int32_t nrep,
-                                                          const T* __restrict__ fields,
-                                                          const double2* __restrict__ tw, double2* spec)
+// One pass of the 3D transform along AXIS for packed array `arr`, tile `tile`
+// of replica R.  AXIS 0 builds the packed values from the sampled fields.
+// P2: the line length L and the lines per tile W are powers of two (the
+// index arithmetic is then shifts and masks).
+template <typename T, int AXIS, bool P2>
+__device__ __forceinline__ void fft_pass_body(const RepDev& R, uint32_t tile, uint32_t arr, uint32_t L, uint32_t W,
+                                              const T* __restrict__ fields, const double2* __restrict__ tw,
+                                              double2* spec, double2* lds)
 {
-    extern __shared__ double2 lds[];
-    const int r = replica_of_block(first, nrep, blockIdx.x);
-    const RepDev& R = reps[r];
-    const uint32_t tile = blockIdx.x - first[r];
-    const uint32_t arr = blockIdx.y;
     const uint32_t nx = R.nx, ny = R.ny, nz = R.nz;
-    const uint32_t L = fft_axis_len(AXIS, nx, ny, nz);
-    const uint32_t W = fft_tile_lines(AXIS, L, nx);
     const uint32_t ld = L + 1;
+    const uint32_t lL = P2 ? (uint32_t)__builtin_ctz(L) : 0u, lW = P2 ? (uint32_t)__builtin_ctz(W) : 0u;
     double2* buf = lds;
     double2* twl = lds + W * ld;
     const uint32_t toff = R.tw_offset + (AXIS == 0 ? 0u : (AXIS == 1 ? nx : nx + ny));
@@ -200,13 +207,13 @@ __global__ __launch_bounds__(kBlock) void fft_pass_kernel(const RepDev* reps, co
     const uint32_t tot = W * L;
     auto node_of = [&](uint32_t i, uint32_t& w, uint32_t& j, uint32_t& node) -> bool {
         if (AXIS == 0) {
-            w = i / L;
+            w = P2 ? i >> lL : i / L;
             j = i - w * L;
             const uint32_t row = row0 + w;
             node = row * nx + j;
             return row < ny * nz;
         }
-        j = i / W;
+        j = P2 ? i >> lW : i / W;
         w = i - j * W;
         const uint32_t x = x0 + w;
         node = AXIS == 1 ? x + nx * (j + ny * fixed) : x + nx * (fixed + ny * j);
@@ -238,13 +245,30 @@ __global__ __launch_bounds__(kBlock) void fft_pass_kernel(const RepDev* reps, co
     for (uint32_t q = 0; q < kPer; ++q)
         if (at[q] != ~0u) buf[at[q]] = v[q];
     __syncthreads();
-    fft_lines(buf, twl, L, W, ld);
+    fft_lines<P2>(buf, twl, L, W, ld);
 #pragma unroll
     for (uint32_t q = 0; q < kPer; ++q) {
         const uint32_t i = threadIdx.x + q * kBlock;
         uint32_t w, j, node;
         if (i < tot && node_of(i, w, j, node)) S[node] = buf[w * ld + j];
     }
+}
+
+template <typename T, int AXIS>
+__global__ __launch_bounds__(kBlock) void fft_pass_kernel(const RepDev* reps, const uint32_t* first, int32_t nrep,
+                                                          const T* __restrict__ fields,
+                                                          const double2* __restrict__ tw, double2* spec)
+{
+    extern __shared__ double2 lds[];
+    const int r = replica_of_block(first, nrep, blockIdx.x);
+    const RepDev& R = reps[r];
+    const uint32_t tile = blockIdx.x - first[r];
+    const uint32_t L = fft_axis_len(AXIS, R.nx, R.ny, R.nz);
+    const uint32_t W = fft_tile_lines(AXIS, L, R.nx);
+    if ((L & (L - 1)) == 0 && (W & (W - 1)) == 0)
+        fft_pass_body<T, AXIS, true>(R, tile, blockIdx.y, L, W, fields, tw, spec, lds);
+    else
+        fft_pass_body<T, AXIS, false>(R, tile, blockIdx.y, L, W, fields, tw, spec, lds);
 }
 
 // Fixed-point scale of each spectrum for the current sample: 2^62 / bound,
@@ -257,8 +281,13 @@ __device__ __forceinline__ void spectrum_scales(const double* ssq, double (&scal
     for (int m = 0; m < kSpec; ++m) scale[m] = bound[m] > 0.0 ? 0x1p62 / bound[m] : 0.0;
 }
 
-// Each wavefront takes kBinPoints / 4 consecutive wave vectors, 64 at a time
-// (one per lane, so the loads of k and of -k are contiguous).  Neighbouring
+// Each wavefront takes kBinPoints / 4 consecutive wave vectors of the half
+// space that bin_nodes() describes, 64 at a time (one per lane, so the loads
+// of k and of -k are contiguous).  The spectra of real fields take equal
+// values at k and -k, so a wave vector whose partner -k lies outside that
+// range counts twice, one that is its own partner once, and the upper member
+// of a pair inside the range not at all: every wave vector of the box is
+// counted once, with half the loads.  Neighbouring
 // lanes mostly share a shell: a segmented scan over the lanes, keyed by the
 // shell, sums the five powers of each run of equal shell in FP64, and the last
 // lane of each run adds its rounded fixed-point value to the workgroup's shell
@@ -283,23 +312,25 @@ __global__ __launch_bounds__(kBlock) void spectrum_bin_kernel(const RepDev* reps
     const double2* Z = spec + R.spec_offset;
     const int lane = (int)(threadIdx.x & 63u);
     const uint32_t wave = threadIdx.x >> 6;
+    const uint64_t Nh = bin_nodes(nx, ny, nz);
     const uint32_t base = (blockIdx.x - first[r]) * kBinPoints + wave * (kBinPoints / (kBlock / 64));
     for (uint32_t it = 0; it < kBinPoints / kBlock; ++it) {
         const uint32_t n = base + it * 64u + (uint32_t)lane;
         double v[kSpec] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        uint32_t s = 0;   // 0: k = 0 or past the box (no contribution)
-        if (n < N) {
+        uint32_t s = 0;   // 0: no contribution (k = 0, past the half space, or counted at -k)
+        if (n < Nh) {
             const uint32_t yz = fdiv(n, R.divx);
             const uint32_t x = n - yz * nx;
             const uint32_t z = fdiv(yz, R.divy);
             const uint32_t y = yz - z * ny;
+            // -k
+            const uint32_t mx = x == 0 ? 0 : nx - x, my = y == 0 ? 0 : ny - y, mz = z == 0 ? 0 : nz - z;
+            const uint32_t mn = mx + nx * (my + ny * mz);
             const int64_t fx = signed_freq(x, nx), fy = signed_freq(y, ny), fz = signed_freq(z, nz);
             const uint64_t n2 = (uint64_t)(fx * fx + fy * fy + fz * fz);
-            if (n2 > 0) {
+            if (n2 > 0 && (mn >= Nh || n <= mn)) {
                 s = shell_of(n2);
-                // -k
-                const uint32_t mx = x == 0 ? 0 : nx - x, my = y == 0 ? 0 : ny - y, mz = z == 0 ? 0 : nz - z;
-                const uint32_t mn = mx + nx * (my + ny * mz);
+                const double wk = n == mn ? invn : 2.0 * invn;   // 1/N per wave vector counted
                 double2 X[2 * kFftArrays];
 #pragma unroll
                 for (int c = 0; c < kFftArrays; ++c) {
@@ -312,11 +343,11 @@ __global__ __launch_bounds__(kBlock) void spectrum_bin_kernel(const RepDev* reps
                 // X: drho, jx, jy, jz, pdiag, poff
                 const double2 js = make_double2(X[1].x + X[2].x + X[3].x, X[1].y + X[2].y + X[3].y);
                 auto pw = [](double2 a) { return a.x * a.x + a.y * a.y; };
-                v[0] = pw(X[0]) * invn;
-                v[1] = (pw(X[1]) + pw(X[2]) + pw(X[3])) * (invn / 3.0);
-                v[2] = pw(js) * invn;
-                v[3] = pw(X[4]) * invn;
-                v[4] = pw(X[5]) * invn;
+                v[0] = pw(X[0]) * wk;
+                v[1] = (pw(X[1]) + pw(X[2]) + pw(X[3])) * (wk / 3.0);
+                v[2] = pw(js) * wk;
+                v[3] = pw(X[4]) * wk;
+                v[4] = pw(X[5]) * wk;
             }
         }
         // segmented inclusive scan over the lanes; a run starts where the shell changes

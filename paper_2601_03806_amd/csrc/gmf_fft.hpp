@@ -94,6 +94,15 @@ __host__ __device__ inline int32_t signed_freq(uint32_t i, uint32_t L)
     return 2 * i < L ? (int32_t)i : (int32_t)i - (int32_t)L;
 }
 
+// Wave vectors the binning kernel visits: the planes n_z = 0 .. floor(nz / 2)
+// of the FFT output (index order x fastest).  Every pair {k, -k} has a member
+// there; a pair whose members both lie there (n_z = 0 or nz / 2) is taken at
+// its lower index.
+__host__ __device__ inline uint64_t bin_nodes(uint32_t nx, uint32_t ny, uint32_t nz)
+{
+    return (uint64_t)(nz / 2 + 1) * nx * ny;
+}
+
 // Shells 0 .. smax of a box, smax = round(sqrt(sum_a floor(L_a / 2)^2)).
 __host__ __device__ inline uint32_t box_shells(uint32_t nx, uint32_t ny, uint32_t nz)
 {

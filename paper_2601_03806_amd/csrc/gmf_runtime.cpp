@@ -249,8 +249,7 @@ Layout plan(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
                 L.spec_blocks[a] += fft_tiles(a, nx, ny, nz);
                 L.spec_lds[a] = std::max<size_t>(L.spec_lds[a], fft_lds_bytes(a, nx, ny, nz));
             }
-            const uint64_t n = (uint64_t)nx * ny * nz;
-            L.spec_blocks[3] += (uint32_t)((n + kBinPoints - 1) / kBinPoints);
+            L.spec_blocks[3] += (uint32_t)((bin_nodes(nx, ny, nz) + kBinPoints - 1) / kBinPoints);
             L.spec_lds[3] = std::max<size_t>(L.spec_lds[3], sizeof(unsigned long long) * kSpec * ns);
         }
         L.spec = take(sizeof(double) * 2 * kFftArrays * (size_t)L.total_nodes);
@@ -880,7 +879,8 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
                 spec_first[(size_t)a * (nrep + 1) + r + 1] =
                     spec_first[(size_t)a * (nrep + 1) + r] + fft_tiles(a, R.nx, R.ny, R.nz);
             spec_first[3 * (size_t)(nrep + 1) + r + 1] =
-                spec_first[3 * (size_t)(nrep + 1) + r] + (R.n + kBinPoints - 1) / kBinPoints;
+                spec_first[3 * (size_t)(nrep + 1) + r] +
+                (uint32_t)((bin_nodes(R.nx, R.ny, R.nz) + kBinPoints - 1) / kBinPoints);
         }
         ctx->rdev.push_back(R);
         if (L.sampling) {
