@@ -93,13 +93,28 @@ def time_context(ctx, stream, steps, warmup, torch):
 def run_gpu(args, torch, gmf, wl):
     stream = torch.cuda.Stream()
     out = {}
+    streaming = {"auto": gmf.STREAM_AUTO, "ab": gmf.STREAM_AB, "aa": gmf.STREAM_AA}[args.streaming]
+    if args.workload == "ensemble":
+        # profiling runs of the batched form alone: the 64-replica ensemble
+        we = wl.ensemble()
+        specs = [gmf.ReplicaSpec(*bx.n, rho0=bx.rho0, tau=bx.tau, kbt=bx.kbt, seed=bx.seed) for bx in we.boxes]
+        with gmf.Context(specs, precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune, streaming=streaming) as ctx:
+            print(f"[bench] {we.name}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+            sec = time_context(ctx, stream, args.steps, args.warmup, torch)
+            mass = sum(ctx.stats(r)["mass"] for r in range(len(specs)))
+            mass0 = sum(sp.n * sp.rho0 for sp in specs)
+            out["headline"] = {"seconds": sec, "nodes": we.nodes, "steps": args.steps, "config": ctx.config(),
+                               "mass_drift_rel": abs(mass - mass0) / mass0}
+        torch.cuda.synchronize()
+        return out
     # bandwidth headline: FP32 shifted (FP64 plain in profiling runs of that kernel)
     w = wl.bandwidth_headline(args.precision)
     b = w.boxes[0]
     spec = gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed)
     storage = gmf.STORE_MOMENTS if args.storage == "moments" else gmf.STORE_POPULATIONS
     head_prec = gmf.FP64 if args.precision == "fp64" else gmf.FP32_SHIFTED
-    with gmf.Context([spec], precision=head_prec, stream=stream, tune=args.tune, storage=storage) as ctx:
+    with gmf.Context([spec], precision=head_prec, stream=stream, tune=args.tune, storage=storage,
+                     streaming=streaming) as ctx:
         print(f"[bench] {w.name} ({args.storage}): warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
               flush=True)
         sec = time_context(ctx, stream, args.steps, args.warmup, torch)
@@ -312,8 +327,11 @@ def make_line(args, res) -> dict:
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic (equilibrium fluid at rest, rho0=1, Philox noise)",
-        "config": {"workload": f"d3q27_256cube_{args.precision}_tau0.8", "lattice": [256, 256, 256], "rho0": 1.0,
-                   "tau": 0.8, "kbt": 1e-4, "seed": 1,
+        "config": ({"workload": "d3q27_ensemble_64rep_fp32", "replicas": 64,
+                    "boxes": "32 x 32^3 + 16 x 48^3 + 16 x 64^3", "rho0": 1.0, "kbt": 1e-4, "seeds": "1..64"}
+                   if args.workload == "ensemble" else
+                   {"workload": f"d3q27_256cube_{args.precision}_tau0.8", "lattice": [256, 256, 256], "rho0": 1.0,
+                    "tau": 0.8, "kbt": 1e-4, "seed": 1}) | {
                    "precision": "fp64_plain" if args.precision == "fp64" else "fp32_shifted",
                    "layout": ("ten moments per node, A/B" if args.storage == "moments" else
                               "row-interleaved populations, " + ("in-place AA" if rh["config"]["streaming"] == "AA"
@@ -321,7 +339,8 @@ def make_line(args, res) -> dict:
                    "kernel_config": rh["config"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": profiled(("mstep" if args.storage == "moments" else "step") + f"_{args.precision}_256",
+                     "traffic": profiled(("mstep" if args.storage == "moments" else "step") + f"_{args.precision}_" +
+                                         ("ensemble" if args.workload == "ensemble" else "256"),
                                          rh["nodes"], rh["config"])},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "mass_drift_rel": rh["mass_drift_rel"],
@@ -342,6 +361,7 @@ def make_line(args, res) -> dict:
         line["fp32_batched"] = {"workload": r["workload"], "replicas": 64, "glups": round(g, 4),
                                 "ms_per_step": round(r["seconds"] / r["steps"] * 1e3, 5),
                                 "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                                "traffic": profiled("step_fp32_ensemble", r["nodes"], r["config"]),
                                 "steps": r["steps"], "kernel_config": r["config"]}
     if "batched_mom" in res:
         r = res["batched_mom"]
@@ -414,11 +434,17 @@ def parse_args(argv=None):
                     help="storage of the FP32 256^3 headline run (moments: profiling of the moment-storage kernel)")
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32",
                     help="precision of the 256^3 headline run (fp64: profiling of the FP64 kernel, with --skip-extra)")
+    ap.add_argument("--streaming", choices=("auto", "ab", "aa"), default="auto",
+                    help="streaming pattern of the headline run (auto: A/B, or the tuner's choice with --tune 1)")
+    ap.add_argument("--workload", choices=("box", "ensemble"), default="box",
+                    help="headline run: the 256^3 box, or the 64-replica FP32 ensemble (profiling, with --skip-extra)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain device copy of one population buffer (bandwidth reference)")
     args = ap.parse_args(argv)
     if args.precision == "fp64" and not args.skip_extra:
         ap.error("--precision fp64 profiles the FP64 kernel alone: add --skip-extra")
+    if args.workload == "ensemble" and (not args.skip_extra or args.precision != "fp32" or args.storage != "populations"):
+        ap.error("--workload ensemble profiles the FP32 population kernel of the ensemble alone: add --skip-extra")
     return args
 
 

@@ -71,6 +71,10 @@ def test_fp64_and_moment_profiling_lines():
     line = bench.make_line(bench.parse_args(["--precision", "fp64", "--skip-extra"]), {"headline": res["headline"]})
     assert line["dtype"] == "f64" and line["config"]["workload"] == "d3q27_256cube_fp64_tau0.8"
     assert abs(line["roofline"]["achieved"] - 432 * N256 / 0.6e-3 / 1e9) < 0.1
+    ens = dict(res["batched"], mass_drift_rel=0.0)
+    line = bench.make_line(bench.parse_args(["--workload", "ensemble", "--skip-extra"]), {"headline": ens})
+    assert line["config"]["workload"] == "d3q27_ensemble_64rep_fp32" and line["config"]["replicas"] == 64
+    assert abs(line["roofline"]["achieved"] - 216 * 7012352 / (0.53 / 2000) / 1e9) < 0.1
     head = dict(res["mom_fp32"], mass_drift_rel=0.0)
     line = bench.make_line(bench.parse_args(["--storage", "moments", "--skip-extra"]), {"headline": head})
     assert abs(line["roofline"]["achieved"] - 80 * N256 / (0.24 / 500) / 1e9) < 0.1
@@ -81,5 +85,8 @@ def test_multi_gpu_request_exits_with_a_message():
                          text=True, timeout=120)
     assert run.returncode == 2 and "one GPU" in run.stderr
     run = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--precision", "fp64"],
+                         capture_output=True, text=True, timeout=120)
+    assert run.returncode == 2 and "--skip-extra" in run.stderr
+    run = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "ensemble"],
                          capture_output=True, text=True, timeout=120)
     assert run.returncode == 2 and "--skip-extra" in run.stderr
