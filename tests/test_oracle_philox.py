@@ -1,12 +1,20 @@
 """Pins of the oracle's noise generator.
 
-Philox4x32-10 is checked against an independent pure-Python implementation of
-the SC'11 description (Salmon, Moraes, Dror, Shaw), the counter and key layout
-against its definition, and the words for uniformity.  The Box-Muller normals
+Philox4x32-10 is checked against a third-party implementation, rocRAND's
+engine (header-only source of the ROCm installation, compiled for the host
+with g++: tests/c/rocrand_philox_ref.cpp), word for word, including the
+counter layout (node, step low word, block, step high word) of the noise
+words; also against a pure-Python implementation of the SC'11 description
+(Salmon, Moraes, Dror, Shaw), the counter and key layout against its
+definition, and the words for uniformity.  The Box-Muller normals
 are checked for their distribution and against the transform written out from
 the words.  (The device generator is checked word for word against the oracle
 in the GPU tests.)
 """
+import os
+import shutil
+import subprocess
+
 import numpy as np
 import pytest
 from scipy import stats
@@ -29,6 +37,51 @@ def philox_ref(ctr, key, rounds=10):
         p1 = m1 * x[2]
         x = [((p1 >> 32) ^ x[1] ^ k[0]) & MASK, p1 & MASK, ((p0 >> 32) ^ x[3] ^ k[1]) & MASK, p0 & MASK]
     return x
+
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROCRAND = "/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"
+
+
+@pytest.fixture(scope="module")
+def rocrand_ref(tmp_path_factory):
+    """Path of the rocRAND-engine reference program, built with g++."""
+    if not os.path.exists(ROCRAND) or shutil.which("g++") is None:
+        pytest.skip("rocRAND headers or g++ not available")
+    exe = str(tmp_path_factory.mktemp("rocrand") / "philox_ref")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                    os.path.join(ROOT, "tests", "c", "rocrand_philox_ref.cpp"), "-o", exe], check=True)
+    return exe
+
+
+def _rocrand_words(exe, cases):
+    """cases: (seed, c0, c1, c2, c3) with c1 < 2^30 -> list of 4-word lists."""
+    text = "".join(" ".join(str(int(v)) for v in c) + "\n" for c in cases)
+    run = subprocess.run([exe], input=text, capture_output=True, text=True, timeout=60, check=True)
+    return [[int(v) for v in line.split()] for line in run.stdout.strip().split("\n")]
+
+
+def test_philox_matches_rocrand_engine(rocrand_ref):
+    rng = np.random.default_rng(7)
+    cases = [(0, 0, 0, 0, 0), (1, 0, 0, 0, 0), (2 ** 64 - 1, 2 ** 32 - 1, 2 ** 30 - 1, 2 ** 32 - 1, 2 ** 32 - 1)]
+    for _ in range(200):
+        cases.append((int(rng.integers(0, 2 ** 63)) * 2 + int(rng.integers(0, 2)), int(rng.integers(0, 2 ** 32)),
+                      int(rng.integers(0, 2 ** 30)), int(rng.integers(0, 2 ** 32)), int(rng.integers(0, 2 ** 32))))
+    ref = _rocrand_words(rocrand_ref, cases)
+    for c, r in zip(cases, ref):
+        key = np.array([c[0] & MASK, c[0] >> 32], np.uint32)
+        assert list(map(int, oracle.philox(np.array(c[1:], np.uint32), key))) == r, c
+
+
+def test_noise_words_layout_matches_rocrand_engine(rocrand_ref):
+    """The noise words of (seed, node, step, block) are Philox4x32-10 at counter
+    (node, step mod 2^32, block, step div 2^32): steps below and above 2^32."""
+    picks = [(1, 0, 0, 0), (42, 4095, 199, 5), (2 ** 40 + 3, 2 ** 31 + 7, 2 ** 32 + 11, 3),
+             (2 ** 64 - 1, 2 ** 32 - 1, 5 * 2 ** 32 + 2 ** 29, 1)]
+    cases = [(s, n, t & MASK, b, t >> 32) for s, n, t, b in picks]
+    ref = _rocrand_words(rocrand_ref, cases)
+    for (s, n, t, b), r in zip(picks, ref):
+        assert list(map(int, oracle.noise_words(s, n, t, b))) == r, (s, n, t, b)
 
 
 def test_philox_matches_independent_implementation():
