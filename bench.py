@@ -57,7 +57,9 @@ def variant_key(cfg: dict) -> str:
     """Step-kernel variant as named in profiles/traffic.json."""
     if cfg.get("storage") == "moments":
         return f"moments/{cfg['tile']}/{cfg['block_map']}"
-    return f"{cfg['addressing']}/{cfg['streaming']}/npt{cfg['nodes_per_thread']}/{cfg['block_map']}"
+    occ = cfg.get("workgroups_per_cu", 0)
+    return (f"{cfg['addressing']}/{cfg['streaming']}/npt{cfg['nodes_per_thread']}/{cfg['block_map']}" +
+            (f"/occ{occ}" if occ else ""))
 
 
 def profiled(kernel_key: str, nodes: int, cfg: dict, field: str = "bytes_per_launch"):

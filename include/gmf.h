@@ -47,6 +47,8 @@
  *   GMF_BLOCK_MAP    linear | xcd | xcd16: force the workgroup-to-XCD mapping
  *   GMF_MTILE        "tile,depth": force the moment-storage tiling (tile 0..3
  *                    = 64x8, 32x16, 32x8, 64x16; depth >= 16 planes)
+ *   GMF_OCCUPANCY    0 | 5 | 4 | 3: force the occupancy cap of the population
+ *                    step (workgroups per CU; 0: none)
  *   GMF_DEBUG        print each failing HIP call to stderr
  * The autotuner (tune = 1) overrides the forced choices it searches.
  */
@@ -266,6 +268,12 @@ int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int3
  * marched over tile_z z planes (0, 0, 0 for population storage).  Any output
  * pointer may be NULL. */
 int gmf_get_tiling(gmf_ctx* ctx, int32_t* storage, int32_t* tile_x, int32_t* tile_y, int32_t* tile_z);
+/* Occupancy cap of the population step kernel: at most *workgroups_per_cu
+ * workgroups of it run on one compute unit at a time (5, 4 or 3), or 0 for no
+ * cap (also with moment storage).  The autotuner (tune = 1) times the caps
+ * for the variant it chose: fewer concurrent workgroups can stream HBM
+ * faster.  GMF_EINVAL if the pointer is NULL. */
+int gmf_get_occupancy(gmf_ctx* ctx, int32_t* workgroups_per_cu);
 
 /* Bandwidth reference: enqueue one plain streaming copy of `bytes` (a positive
  * multiple of 16) from device buffer src to device buffer dst (both 16-byte

@@ -43,6 +43,7 @@ EXPORTED = (
     "gmf_workspace_bytes", "gmf_init", "gmf_step", "gmf_moments", "gmf_stats", "gmf_reset_stats",
     "gmf_get_populations", "gmf_set_populations", "gmf_get_nodes", "gmf_get_step", "gmf_noise_probe",
     "gmf_get_config", "gmf_copy_probe", "gmf_destroy", "gmf_strerror", "gmf_spectrum", "gmf_get_tiling",
+    "gmf_get_occupancy",
 )
 
 
@@ -105,6 +106,7 @@ def lib() -> ctypes.CDLL:
                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32), dp]
         L.gmf_get_config.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 6
         L.gmf_get_tiling.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 4
+        L.gmf_get_occupancy.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
         L.gmf_spectrum.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp, ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int32)]
         L.gmf_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, vp]
@@ -115,7 +117,7 @@ def lib() -> ctypes.CDLL:
         L.gmf_strerror.restype = ctypes.c_char_p
         for name in ("gmf_init", "gmf_step", "gmf_moments", "gmf_stats", "gmf_reset_stats",
                      "gmf_get_populations", "gmf_set_populations", "gmf_get_nodes", "gmf_get_step",
-                     "gmf_noise_probe", "gmf_get_config", "gmf_spectrum", "gmf_get_tiling"):
+                     "gmf_noise_probe", "gmf_get_config", "gmf_spectrum", "gmf_get_tiling", "gmf_get_occupancy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -257,11 +259,14 @@ class Context:
         st, tx, ty, tz = (ctypes.c_int32() for _ in range(4))
         _check(lib().gmf_get_tiling(self._h, ctypes.byref(st), ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(tz)),
                "gmf_get_tiling")
+        occ = ctypes.c_int32()
+        _check(lib().gmf_get_occupancy(self._h, ctypes.byref(occ)), "gmf_get_occupancy")
         cfg = {"nodes_per_thread": a.value, "block": b.value, "graph_steps": c.value,
                "addressing": "plane" if d.value == 0 else ("none" if d.value < 0 else f"group{d.value}"),
                "streaming": "AA" if e.value == STREAM_AA else "A/B",
                "block_map": f"xcd/{x.value}" if x.value else "linear",
-               "storage": "moments" if st.value == STORE_MOMENTS else "populations"}
+               "storage": "moments" if st.value == STORE_MOMENTS else "populations",
+               "workgroups_per_cu": occ.value}
         if st.value == STORE_MOMENTS:
             cfg["tile"] = f"{tx.value}x{ty.value}x{tz.value}"
         return cfg

@@ -35,7 +35,25 @@ struct StepArgs {
                                   // each taking runs of `chunk` consecutive blocks
     uint32_t chunk;               // blocks per run (0: one contiguous range per XCD)
     uint32_t tz;                  // moment storage: z planes per tile
+    uint32_t occ;                 // population step: at most occ workgroups per CU (0: no cap);
+                                  // a launch parameter only (see occ_lds_bytes)
 };
+
+// Occupancy caps of the population step kernel that the autotuner tries: at
+// most k workgroups per CU, k in kOccCap (0: no cap).  The kernel uses no LDS;
+// a cap is enforced by reserving LDS at launch, midway between what k + 1 and
+// k workgroups fill of the 160 KiB of a gfx950 CU (always under the 64 KiB a
+// workgroup may take).
+constexpr int kOccCaps = 4;
+constexpr uint32_t kOccCap[kOccCaps] = {0u, 5u, 4u, 3u};
+constexpr uint32_t occ_lds_bytes(uint32_t k)
+{
+    return k == 0 ? 0u : ((160u * 1024u / (k + 1u) + 160u * 1024u / k) / 2u) / 256u * 256u;
+}
+static_assert(occ_lds_bytes(3) < 64u * 1024u && occ_lds_bytes(3) * 3u <= 160u * 1024u &&
+                  occ_lds_bytes(3) * 4u > 160u * 1024u,
+              "three workgroups per CU");
+static_assert(occ_lds_bytes(5) * 5u <= 160u * 1024u && occ_lds_bytes(5) * 6u > 160u * 1024u, "five workgroups per CU");
 
 // Moment storage (gmf_mstep.hip): the state is kMom fields of N values per
 // replica, the raw moments of g = f - w rho0 of the pre-collision state:
@@ -65,6 +83,7 @@ constexpr int mtile_threads(int t)
 // grp: addressing mode shared by every replica of the context: 0 (plane-uniform,
 // storage groups of 27) or the storage group size 27, 3 or 1 (per-node addressing)
 // a.xcd > 0: the grid is rounded up to whole chunks on every XCD (see step_kernel)
+// a.occ > 0: at most a.occ workgroups per CU (occ_lds_bytes)
 hipError_t launch_step(int precision, int collision, bool sample, int sm, int grp, int npt, const StepArgs& a,
                        uint32_t nblocks, hipStream_t s);
 hipError_t launch_init(int precision, void* buf, const RepDev* rep_dev, const RepDev& rep, hipStream_t s);

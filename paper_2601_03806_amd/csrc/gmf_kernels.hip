@@ -245,9 +245,11 @@ static hipError_t launch_step_npt(int npt, const StepArgs& a, uint32_t nblocks, 
         b.chunk = a.chunk ? a.chunk : (nblocks + a.xcd - 1u) / a.xcd;
         g = (nblocks + a.xcd * b.chunk - 1u) / (a.xcd * b.chunk) * b.chunk * a.xcd;
     }
+    // LDS the kernel does not touch, reserved only to cap the workgroups per CU
+    const uint32_t lds = occ_lds_bytes(a.occ);
     switch (npt) {
-    case 1: step_kernel<T, SHIFTED, COLL, SAMPLE, 1, G, SM><<<g, kBlock, 0, s>>>(b); break;
-    case 2: step_kernel<T, SHIFTED, COLL, SAMPLE, 2, G, SM><<<g, kBlock, 0, s>>>(b); break;
+    case 1: step_kernel<T, SHIFTED, COLL, SAMPLE, 1, G, SM><<<g, kBlock, lds, s>>>(b); break;
+    case 2: step_kernel<T, SHIFTED, COLL, SAMPLE, 2, G, SM><<<g, kBlock, lds, s>>>(b); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -292,6 +294,9 @@ hipError_t launch_step(int precision, int collision, bool sample, int sm, int gr
 {
     // the AA patterns update one buffer in place
     if (sm != kAB && a.src != a.dst) return hipErrorInvalidValue;
+    bool occ_known = false;
+    for (uint32_t k : kOccCap) occ_known = occ_known || a.occ == k;
+    if (!occ_known) return hipErrorInvalidValue;
     if (precision == kFP64) return launch_step_t<double, false>(collision, sample, sm, grp, npt, a, nblocks, s);
     return launch_step_t<float, true>(collision, sample, sm, grp, npt, a, nblocks, s);
 }

@@ -310,6 +310,7 @@ struct gmf_ctx {
     uint32_t mtz = kDefaultMTz;    // moment storage: z planes per tile
     uint32_t xcd_count = 1;        // XCDs of the device
     int xcd_map = 0;               // workgroup mapping: 0 linear, else an index into kXcdChunks
+    uint32_t occ = 0;              // population step: workgroups per CU cap (kOccCap; 0: none)
     uint32_t nblocks = 0;          // lattice grid for the current npt
     int graph_steps = 0;           // 0: direct launches
     int period = 2;                // step pattern period (A/B parity, sampling)
@@ -410,6 +411,7 @@ int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
     a.xcd = ctx->xcd_map ? ctx->xcd_count : 0u;
     a.chunk = kXcdChunks[ctx->xcd_map];
     a.tz = ctx->mtz;
+    a.occ = ctx->mom ? 0u : ctx->occ;
     const bool sample = sampling_step(ctx, t);
     if (ctx->mom)
         CK(launch_mstep(ctx->opt.precision, sample, ctx->mtile, a, ctx->nblocks, ctx->stream));
@@ -518,22 +520,23 @@ int init_state(gmf_ctx* ctx)
     return GMF_OK;
 }
 
-// Autotuner support shared by both storages.  A candidate is up to four
+// Autotuner support shared by both storages.  A candidate is up to five
 // integer parameters.  The file named by GMF_TUNE_CACHE caches choices as
-// lines "key v0 v1 v2 v3"; the last line for a key whose parameters still
-// fit the context is used.
-using TuneParams = std::array<int, 4>;
+// lines "key v0 v1 v2 v3 v4"; the last line for a key whose parameters still
+// fit the context is used, and lines of any other form are skipped.
+using TuneParams = std::array<int, 5>;
 
 bool tune_cache_read(const std::string& key, const std::function<bool(const TuneParams&)>& valid, TuneParams* out)
 {
     const char* path = getenv("GMF_TUNE_CACHE");
     FILE* fh = path ? fopen(path, "r") : nullptr;
     if (!fh) return false;
-    char k[4096];
+    char line[8192], k[4096], extra[2];
     TuneParams v;
     bool found = false;
-    while (fscanf(fh, "%4095s %d %d %d %d", k, &v[0], &v[1], &v[2], &v[3]) == 5)
-        if (key == k && valid(v)) {
+    while (fgets(line, sizeof(line), fh))
+        if (sscanf(line, "%4095s %d %d %d %d %d %1s", k, &v[0], &v[1], &v[2], &v[3], &v[4], extra) == 6 && key == k &&
+            valid(v)) {
             *out = v;
             found = true;
         }
@@ -545,7 +548,7 @@ void tune_cache_append(const std::string& key, const TuneParams& v)
 {
     const char* path = getenv("GMF_TUNE_CACHE");
     if (FILE* fh = path ? fopen(path, "a") : nullptr) {
-        fprintf(fh, "%s %d %d %d %d\n", key.c_str(), v[0], v[1], v[2], v[3]);
+        fprintf(fh, "%s %d %d %d %d %d\n", key.c_str(), v[0], v[1], v[2], v[3], v[4]);
         fclose(fh);
     }
 }
@@ -602,8 +605,9 @@ bool contains(const std::vector<int>& v, int x) { return std::find(v.begin(), v.
 
 // Population storage: time every fitting (addressing mode, nodes per thread,
 // streaming pattern, workgroup-to-XCD mapping) combination on the initial
-// state, keep the fastest, and restore the initial state in the chosen
-// layout.  A/B re-runs the same step from the same source buffer; AA
+// state without an occupancy cap; then, for the fastest addressing mode and
+// nodes per thread, every (streaming pattern, mapping, occupancy cap
+// (kOccCap)); keep the fastest and restore the initial state in its layout.  A/B re-runs the same step from the same source buffer; AA
 // alternates its two step kinds in place (the state then changes, which does
 // not matter for the timing and is undone by the re-initialisation).  AA is a
 // candidate only when the options leave the pattern open; A/B only when the
@@ -614,25 +618,26 @@ int autotune(gmf_ctx* ctx)
     std::vector<int> patterns;
     if (ctx->opt.streaming != GMF_STREAM_AA) patterns.push_back(GMF_STREAM_AB);
     if (ctx->opt.streaming != GMF_STREAM_AB) patterns.push_back(GMF_STREAM_AA);
-    const std::string key = "v3p" + std::to_string(ctx->opt.precision) + "c" + std::to_string(ctx->opt.collision) +
+    const std::string key = "v4p" + std::to_string(ctx->opt.precision) + "c" + std::to_string(ctx->opt.collision) +
                             "s" + std::to_string(ctx->opt.streaming) + boxes_key(ctx);
     std::vector<int> maps = {0};
     if (ctx->xcd_count > 1)
         for (int xm = 1; xm < kXcdMaps; ++xm) maps.push_back(xm);
-    // parameters: addressing mode, nodes per thread, streaming pattern, mapping
+    std::vector<int> caps(kOccCap, kOccCap + kOccCaps);
+    // parameters: addressing mode, nodes per thread, streaming pattern, mapping, occupancy cap
     auto fits = [&](const TuneParams& v) {
         return contains({27, 0, 3, 1}, v[0]) && (v[1] == 1 || v[1] == 2) &&
                mode_fits(ctx->reps.data(), ctx->nrep, es, v[0], v[1]) && contains(patterns, v[2]) &&
-               contains(maps, v[3]);
+               contains(maps, v[3]) && contains(caps, v[4]);
     };
-    TuneParams best = {ctx->mode, ctx->npt, ctx->aa ? GMF_STREAM_AA : GMF_STREAM_AB, ctx->xcd_map};
+    TuneParams best = {ctx->mode, ctx->npt, ctx->aa ? GMF_STREAM_AA : GMF_STREAM_AB, ctx->xcd_map, (int)ctx->occ};
     if (!tune_cache_read(key, fits, &best)) {
         std::vector<TuneParams> cands;
         for (int pat : patterns)
             for (int m : {27, 0, 3, 1})
                 for (int c : {1, 2})
                     for (int xm : maps)
-                        if (fits({m, c, pat, xm})) cands.push_back({m, c, pat, xm});
+                        if (fits({m, c, pat, xm, 0})) cands.push_back({m, c, pat, xm, 0});
         StepArgs a;
         auto configure = [&](const TuneParams& v) {
             set_layout(ctx, v[0]);
@@ -646,6 +651,7 @@ int autotune(gmf_ctx* ctx)
             a.nblocks = ctx->nblocks;
             a.xcd = v[3] ? ctx->xcd_count : 0u;
             a.chunk = kXcdChunks[v[3]];
+            a.occ = (uint32_t)v[4];
             return rc;
         };
         auto launch = [&](const TuneParams& v, int i) {
@@ -653,12 +659,22 @@ int autotune(gmf_ctx* ctx)
             return launch_step(ctx->opt.precision, ctx->opt.collision, false, sm, v[0], v[1], a, ctx->nblocks,
                                ctx->stream);
         };
-        const int rc = tune_time(ctx, cands, configure, launch, &best);
+        int rc = tune_time(ctx, cands, configure, launch, &best);
+        if (rc != GMF_OK) return rc;
+        // second stage: the chosen addressing mode and nodes per thread with
+        // every streaming pattern, mapping and occupancy cap (the mapping that
+        // wins without a cap need not win with one)
+        std::vector<TuneParams> occs;
+        for (int pat : patterns)
+            for (int xm : maps)
+                for (uint32_t k : kOccCap) occs.push_back({best[0], best[1], pat, xm, (int)k});
+        rc = tune_time(ctx, occs, configure, launch, &best);
         if (rc != GMF_OK) return rc;
         tune_cache_append(key, best);
     }
     ctx->aa = best[2] == GMF_STREAM_AA;
     ctx->xcd_map = best[3];
+    ctx->occ = (uint32_t)best[4];
     set_layout(ctx, best[0]);
     const int rc = build_grid(ctx, best[1]);
     if (rc != GMF_OK) return rc;
@@ -671,7 +687,7 @@ int autotune(gmf_ctx* ctx)
 int autotune_moments(gmf_ctx* ctx)
 {
     const size_t es = ctx->opt.precision == GMF_FP32_SHIFTED ? 4 : 8;
-    const std::string key = "m2p" + std::to_string(ctx->opt.precision) + boxes_key(ctx);
+    const std::string key = "m3p" + std::to_string(ctx->opt.precision) + boxes_key(ctx);
     // the halo columns a tile reads again are L2 hits only when neighbouring
     // tiles run on the same XCD: with several XCDs only the XCD mappings are
     // tried (the linear one measured 1.66x the algorithmic reads at 256^3)
@@ -680,17 +696,18 @@ int autotune_moments(gmf_ctx* ctx)
         for (int xm = 1; xm < kXcdMaps; ++xm) maps.push_back(xm);
     else
         maps.push_back(0);
-    // parameters: tile shape, tile depth, mapping, unused
+    // parameters: tile shape, tile depth, mapping, two unused
     auto fits = [&](const TuneParams& v) {
-        return v[0] >= 0 && v[0] < kMTiles && mtile_fits(v[0], es) && v[1] >= (int)kMTz[0] && contains(maps, v[2]);
+        return v[0] >= 0 && v[0] < kMTiles && mtile_fits(v[0], es) && v[1] >= (int)kMTz[0] && contains(maps, v[2]) &&
+               v[3] == 0 && v[4] == 0;
     };
-    TuneParams best = {ctx->mtile, (int)ctx->mtz, maps.front(), 0};
+    TuneParams best = {ctx->mtile, (int)ctx->mtz, maps.front(), 0, 0};
     if (!tune_cache_read(key, fits, &best)) {
         std::vector<TuneParams> cands;
         for (int tl = 0; tl < kMTiles; ++tl)
             for (uint32_t tz : kMTz)
                 for (int xm : maps)
-                    if (fits({tl, (int)tz, xm, 0})) cands.push_back({tl, (int)tz, xm, 0});
+                    if (fits({tl, (int)tz, xm, 0, 0})) cands.push_back({tl, (int)tz, xm, 0, 0});
         StepArgs a;
         auto configure = [&](const TuneParams& v) {
             ctx->mtile = v[0];
@@ -819,6 +836,13 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
     // moment storage reads the halo columns of a tile again: by default each
     // XCD takes runs of neighbouring tiles, so that those reads hit its L2
     if (ctx->mom && ctx->xcd_count > 1) ctx->xcd_map = 2;
+    // GMF_OCCUPANCY = k forces an occupancy cap of the population step (tests;
+    // k in kOccCap, 0: none)
+    if (const char* forced = getenv("GMF_OCCUPANCY")) {
+        const int k = atoi(forced);
+        for (uint32_t c : kOccCap)
+            if ((int)c == k) ctx->occ = c;
+    }
     // GMF_BLOCK_MAP = linear | xcd | xcd16 forces the workgroup-to-block mapping (tests)
     if (const char* forced = getenv("GMF_BLOCK_MAP")) {
         ctx->xcd_map = 0;
@@ -1178,6 +1202,14 @@ int gmf_get_config(gmf_ctx* ctx, int32_t* nodes_per_thread, int32_t* block, int3
     if (block) *block = ctx->mom ? mtile_threads(ctx->mtile) : kBlock;
     if (graphs) *graphs = ctx->graph_steps;
     if (addressing) *addressing = ctx->mom ? -1 : ctx->mode;
+    return GMF_OK;
+}
+
+int gmf_get_occupancy(gmf_ctx* ctx, int32_t* workgroups_per_cu)
+{
+    if (!ctx) return GMF_ESTATE;
+    if (!workgroups_per_cu) return GMF_EINVAL;
+    *workgroups_per_cu = ctx->mom ? 0 : (int32_t)ctx->occ;
     return GMF_OK;
 }
 

@@ -108,5 +108,6 @@ def test_init_rejects_before_touching_the_device():
     # NULL context
     assert lib.gmf_step(None, 1) == gmf.GMF_ESTATE
     assert lib.gmf_stats(None, 0, None) == gmf.GMF_ESTATE
+    assert lib.gmf_get_occupancy(None, None) == gmf.GMF_ESTATE
     assert lib.gmf_noise_probe(1, 0, 0, -1, 0, None, None) == gmf.GMF_EINVAL
     assert gmf.strerror(gmf.GMF_EUNSTABLE).startswith("non-finite")

@@ -122,7 +122,8 @@ def test_graph_equals_direct_bitwise():
 def test_addressing_modes_bitwise(monkeypatch):
     """Plane-uniform and per-node addressing with storage groups of 27, 3 and 1
     give bit-identical trajectories (the layout changes, the arithmetic does
-    not); the autotuner's choice too."""
+    not); so do the workgroup mappings, the occupancy caps and the autotuner's
+    choice."""
     spec = gmf.ReplicaSpec(16, 32, 6, 1.0, 0.6, 1e-4, 21)      # plane of 512 nodes: every mode fits
     for prec in (gmf.FP64, gmf.FP32_SHIFTED):
         out = {}
@@ -149,7 +150,17 @@ def test_addressing_modes_bitwise(monkeypatch):
         with gmf.Context([spec], precision=prec, tune=1) as ctx:
             ctx.step(12)
             out["tuned"] = ctx.get_populations()
-        for mode in ("plane", "27", "3", "1", "xcdplane", "xcd27", "xcd16plane", "xcd1627", "tuned"):
+        # occupancy caps of the step kernel (LDS reserved at launch)
+        for cap in ("5", "4", "3"):
+            monkeypatch.setenv("GMF_OCCUPANCY", cap)
+            say(f"occupancy cap {cap} prec={prec}")
+            with gmf.Context([spec], precision=prec) as ctx:
+                assert ctx.config()["workgroups_per_cu"] == int(cap)
+                ctx.step(12)
+                out["occ" + cap] = ctx.get_populations()
+        monkeypatch.delenv("GMF_OCCUPANCY")
+        for mode in ("plane", "27", "3", "1", "xcdplane", "xcd27", "xcd16plane", "xcd1627", "tuned", "occ5", "occ4",
+                     "occ3"):
             assert np.array_equal(out[""], out[mode]), mode
 
 
@@ -300,7 +311,8 @@ def test_tune_cache(tmp_path, monkeypatch):
     cached choice without timing again and reproduces the trajectory bit for
     bit, for population and moment storage."""
     cache = tmp_path / "tune.txt"
-    cache.write_text("v3p1c0s0_24x20x18 99 1 1 0\nm2p1_24x20x18 7 64 1 0\n")
+    # unfit entries (addressing mode 99, tile 7) and a line of an older format
+    cache.write_text("v4p1c0s0_24x20x18 99 1 1 0 0\nm3p1_24x20x18 7 64 1 0 0\nv4p1c0s0_24x20x18 27 1 1\n")
     monkeypatch.setenv("GMF_TUNE_CACHE", str(cache))
     spec = gmf.ReplicaSpec(24, 20, 18, 1.0, 0.8, 1e-4, 6)
     for storage in (gmf.STORE_POPULATIONS, gmf.STORE_MOMENTS):
