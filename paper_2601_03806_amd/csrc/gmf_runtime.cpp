@@ -32,6 +32,7 @@ constexpr size_t kAlign = 256;
 constexpr size_t kStageCap = 64ull << 20;   // staging for host transfers (per chunk of z planes)
 constexpr int kDefaultGraphSteps = 64;
 constexpr int kDefaultNpt = 1;
+constexpr float kTuneMargin = 0.01f;   // relative gain a later tuning candidate needs to win
 // workgroup mappings: linear, one contiguous range per XCD, runs of 16 blocks per XCD
 constexpr int kXcdMaps = 3;
 constexpr uint32_t kXcdChunks[kXcdMaps] = {0u, 0u, 16u};
@@ -566,7 +567,10 @@ struct EventPair {
 // transient slowdown does not decide the choice (the faster round counts):
 // `configure` sets the context up for a candidate, `launch(c, i)` enqueues its
 // step number i; two steps warm up, eight are timed (an even count, so that
-// AA runs whole pull/local pairs).  *best receives the fastest candidate.
+// AA runs whole pull/local pairs).  *best receives the fastest candidate,
+// where a candidate displaces an earlier one only when it is faster by more
+// than kTuneMargin: near-ties go to the earlier candidate, so the choice does
+// not follow timing noise from one context to the next.
 int tune_time(gmf_ctx* ctx, const std::vector<TuneParams>& cands, const std::function<int(const TuneParams&)>& configure,
               const std::function<hipError_t(const TuneParams&, int)>& launch, TuneParams* best)
 {
@@ -590,7 +594,10 @@ int tune_time(gmf_ctx* ctx, const std::vector<TuneParams>& cands, const std::fun
             CK(hipEventElapsedTime(&t, ev.e0, ev.e1));
             ms[c] = std::min(ms[c], t);
         }
-    *best = cands[std::min_element(ms.begin(), ms.end()) - ms.begin()];
+    size_t bi = 0;
+    for (size_t c = 1; c < cands.size(); ++c)
+        if (ms[c] < ms[bi] * (1.0f - kTuneMargin)) bi = c;
+    *best = cands[bi];
     return GMF_OK;
 }
 
