@@ -186,3 +186,38 @@ def test_fdt_fixed_point_one_step(tabs, coll, tau):
     Qn = lat.noise_cov(tau, kbt, bgk=(coll == oracle.BGK))
     S0 = mu * np.diag(w)
     np.testing.assert_allclose(C @ S0 @ C.T + Qn, S0, atol=1e-14 * mu)
+
+
+@pytest.mark.parametrize("coll", [oracle.GMF, oracle.BGK])
+@pytest.mark.parametrize("tau", [0.55, 1.0, 3.0])
+def test_noise_rho_option_scales_amplitudes(tabs, coll, tau):
+    """Eqs. (2) and (9) carry the density under a square root.  With noise_rho = 0
+    the local rho of Eq. (3) enters, with noise_rho = 1 the reference rho0.  The
+    noise part of f* (f* at k_BT > 0 minus f* at k_BT = 0, same node and step)
+    is linear in the amplitudes, so mode by mode:
+      noise(noise_rho = 1) = sqrt(rho0 / rho) * noise(noise_rho = 0),
+    and under noise_rho = 1 it does not depend on the local density at all."""
+    vel, w, e, b, *_ = tabs
+    rng = np.random.default_rng(int(tau * 100) + 7 * coll)
+    rho0 = 1.3
+    for node, target in enumerate((0.55, 0.9, 1.2, 1.45, 1.8, 2.6)):
+        f = _random_state(rng, w)
+        f *= target / f.sum()               # local rho far from rho0
+        rho = f.sum()
+        det = oracle.collide(f, oracle.params(1, rho0=rho0, tau=tau, kbt=0.0, collision=coll), node, 11)
+
+        def noise_part(nr, ff, fdet):
+            p = oracle.params(1, rho0=rho0, tau=tau, kbt=2e-4, seed=23, collision=coll, noise_rho=nr)
+            return e @ (oracle.collide(ff, p, node, 11) - fdet)      # moments k = 0..26
+        m_loc = noise_part(0, f, det)
+        m_ref = noise_part(1, f, det)
+        # differences of O(rho) populations: rounding leaves ~1e-16 * rho in every moment
+        tol = 4e-16 * rho
+        np.testing.assert_allclose(m_loc[:4], 0.0, atol=tol)
+        np.testing.assert_allclose(m_ref[:4], 0.0, atol=tol)
+        np.testing.assert_allclose(m_ref[4:], np.sqrt(rho0 / rho) * m_loc[4:], rtol=1e-12, atol=tol)
+        # a node with another local density: the rho0 noise is unchanged, the local one scales with sqrt(rho)
+        s = 1.37
+        det2 = oracle.collide(s * f, oracle.params(1, rho0=rho0, tau=tau, kbt=0.0, collision=coll), node, 11)
+        np.testing.assert_allclose(noise_part(1, s * f, det2)[4:], m_ref[4:], rtol=1e-12, atol=s * tol)
+        np.testing.assert_allclose(noise_part(0, s * f, det2)[4:], np.sqrt(s) * m_loc[4:], rtol=1e-12, atol=s * tol)

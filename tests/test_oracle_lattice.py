@@ -186,3 +186,33 @@ def test_equilibrium_values_from_theory(tabs):
     assert abs(v["jx"] @ S @ v["jx"] - 1e-4) < 1e-18
     assert abs(v["pdiag"] @ S @ v["pdiag"] - 5e-4) < 1e-17
     assert abs(v["poff"] @ S @ v["poff"] - 1e-4) < 1e-18
+
+
+@pytest.mark.parametrize("box", [(6, 5, 4), (1, 7, 3)])
+def test_observables_of_known_fields(tabs, box):
+    """oracle_observables on f = f^eq(rho(x), u(x)) built from known fields
+    (Eq. (11)): the equilibrium carries exactly rho, rho u and
+    Pi = rho u u + rho cs2 I, so every per-node observable has a closed form.
+    u_a must be j_a / rho (not j_a / rho0): the density field varies by +-40%."""
+    vel, w, *_ = tabs
+    nx, ny, nz = box
+    N = nx * ny * nz
+    rng = np.random.default_rng(N)
+    rho0 = 1.1
+    rho = rho0 * (1 + 0.4 * rng.uniform(-1, 1, N))
+    u = 0.05 * rng.uniform(-1, 1, (3, N))
+    f = np.empty((27, N))
+    for n in range(N):
+        f[:, n] = oracle.feq(rho[n], u[:, n])
+    p = oracle.params(nx, ny, nz, rho0=rho0)
+    sums, _ = oracle.observables(p, np.ascontiguousarray(f.reshape(-1)))
+    j = rho * u
+    expect = [rho - rho0, j[0], j[1], j[2], j.sum(axis=0),
+              rho * (u * u).sum(axis=0) + 3 * CS2 * (rho - rho0),
+              rho * (u[0] * u[1] + u[0] * u[2] + u[1] * u[2]),
+              u[0], u[1], u[2]]
+    for o, v in enumerate(expect):
+        assert abs(sums[o, 0] - v.sum()) <= 1e-15 * N * max(np.abs(v).max(), 1e-3), (o, sums[o, 0], v.sum())
+        assert abs(sums[o, 1] - (v * v).sum()) <= 1e-15 * N * max((v * v).max(), 1e-6), (o, sums[o, 1], (v * v).sum())
+    # the j / rho0 reading would be off by far more than the tolerance
+    assert abs((j[0] / rho0).sum() - u[0].sum()) > 1e-3

@@ -107,3 +107,34 @@ def test_agrees_with_brute_force_dft_on_common_shells():
         assert cnt[shell] == total
         expect = sum(mult[n2] * brute[:, idx[n2]] for n2 in members) / total
         np.testing.assert_allclose(out[:, shell], expect, rtol=1e-11)
+
+
+def test_brute_force_dft_matches_numpy_fft_on_every_exact_shell():
+    """The C oracle's direct DFT against numpy's orthonormal FFT, restricted to
+    exactly the integer vectors of each shell |n|^2 = 1, 2, 3, 4, 5, 6, 8, 9
+    (8: the 12 vectors (+-2, +-2, 0) and permutations; 9: (+-3, 0, 0) and
+    (+-2, +-2, +-1) and permutations, 30 in all).  Every box length is at
+    least 7, so +-3 are distinct frequencies."""
+    nx, ny, nz = 9, 8, 7
+    N = nx * ny * nz
+    p = oracle.params(nx, ny, nz, rho0=1.0, tau=0.7, kbt=1e-4, seed=5)
+    w = oracle.tables()[1]
+    f = wl.perturbed_populations(w, N, amp=0.05, seed=17, velocity=0.05)
+    oracle.run(p, f, 0, 2)
+    _, brute = oracle.observables(p, f)
+    fl = sp.fields(p, f)
+    jsum = fl["jx"] + fl["jy"] + fl["jz"]
+
+    def power(v):
+        # fields are x-fastest: reshape to (z, y, x) before the FFT
+        return np.abs(np.fft.fftn(v.reshape(nz, ny, nx), norm="ortho")) ** 2
+    pw = {"rho": power(fl["drho"]), "jx": power(fl["jx"]), "jy": power(fl["jy"]), "jz": power(fl["jz"]),
+          "jsum": power(jsum), "pdiag": power(fl["pdiag"]), "poff": power(fl["poff"])}
+    expected_counts = {1: 6, 2: 12, 3: 8, 4: 6, 5: 24, 6: 24, 8: 12, 9: 30}
+    for s, n2 in enumerate(oracle.SHELL_N2):
+        vecs = [v for v in itertools.product(range(-3, 4), repeat=3) if v[0] ** 2 + v[1] ** 2 + v[2] ** 2 == n2]
+        assert len(vecs) == expected_counts[n2]
+        idx = tuple(np.array([(c % nz, b % ny, a % nx) for a, b, c in vecs]).T)
+        expect = [pw["rho"][idx].mean(), (pw["jx"][idx] + pw["jy"][idx] + pw["jz"][idx]).mean() / 3,
+                  pw["jsum"][idx].mean(), pw["pdiag"][idx].mean(), pw["poff"][idx].mean()]
+        np.testing.assert_allclose(brute[:, s], expect, rtol=1e-11, err_msg=f"|n|^2 = {n2}")
