@@ -80,29 +80,50 @@ def profiled(kernel_key: str, nodes: int, cfg: dict, field: str = "bytes_per_lau
     return None if var is None else var.get(field)
 
 
-def time_context(ctx, stream, steps, warmup, torch):
+def graph_len(steps: int, cap: int = 64) -> int:
+    """Steps per captured graph for a timed loop of `steps` steps: the longest
+    length up to `cap` that divides it, so that the loop is whole graph replays."""
+    return next(g for g in range(max(1, min(cap, steps)), 0, -1) if steps % g == 0)
+
+
+def time_context(ctx, stream, steps, warmup, torch, loops=None, key=None):
+    """Seconds for `steps` steps after `warmup` untimed ones.  Every graph the
+    timed steps launch is captured beforehand (gmf_prepare), so the timed
+    region holds graph replays and kernels only; what ran is recorded in
+    loops[key] from the library's launch counters."""
     ctx.step(warmup)
+    ctx.prepare(steps)
     torch.cuda.synchronize()
+    before = ctx.launch_counts()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     ctx.step(steps)
     e1.record(stream)
     torch.cuda.synchronize()
+    after = ctx.launch_counts()
+    if loops is not None:
+        loops[key] = {"steps_per_graph": ctx.config()["graph_steps"],
+                      "graph_replays": after["graph_launches"] - before["graph_launches"],
+                      "graph_steps": after["graph_steps"] - before["graph_steps"],
+                      "direct_steps": after["direct_steps"] - before["direct_steps"],
+                      "captured_in_timed_region": after["graphs_captured"] - before["graphs_captured"]}
     return e0.elapsed_time(e1) / 1e3   # seconds
 
 
 def run_gpu(args, torch, gmf, wl):
     stream = torch.cuda.Stream()
     out = {}
+    loops = out.setdefault("step_loops", {})
     streaming = {"auto": gmf.STREAM_AUTO, "ab": gmf.STREAM_AB, "aa": gmf.STREAM_AA}[args.streaming]
     if args.workload == "ensemble":
         # profiling runs of the batched form alone: the 64-replica ensemble
         we = wl.ensemble()
         specs = [gmf.ReplicaSpec(*bx.n, rho0=bx.rho0, tau=bx.tau, kbt=bx.kbt, seed=bx.seed) for bx in we.boxes]
-        with gmf.Context(specs, precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune, streaming=streaming) as ctx:
+        with gmf.Context(specs, precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune, streaming=streaming,
+                         graph_steps=graph_len(args.steps)) as ctx:
             print(f"[bench] {we.name}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
-            sec = time_context(ctx, stream, args.steps, args.warmup, torch)
+            sec = time_context(ctx, stream, args.steps, args.warmup, torch, loops, "headline")
             mass = sum(ctx.stats(r)["mass"] for r in range(len(specs)))
             mass0 = sum(sp.n * sp.rho0 for sp in specs)
             out["headline"] = {"seconds": sec, "nodes": we.nodes, "steps": args.steps, "config": ctx.config(),
@@ -116,10 +137,10 @@ def run_gpu(args, torch, gmf, wl):
     storage = gmf.STORE_MOMENTS if args.storage == "moments" else gmf.STORE_POPULATIONS
     head_prec = gmf.FP64 if args.precision == "fp64" else gmf.FP32_SHIFTED
     with gmf.Context([spec], precision=head_prec, stream=stream, tune=args.tune, storage=storage,
-                     streaming=streaming) as ctx:
+                     streaming=streaming, graph_steps=graph_len(args.steps)) as ctx:
         print(f"[bench] {w.name} ({args.storage}): warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
               flush=True)
-        sec = time_context(ctx, stream, args.steps, args.warmup, torch)
+        sec = time_context(ctx, stream, args.steps, args.warmup, torch, loops, "headline")
         st = ctx.stats()
         out["headline"] = {"seconds": sec, "nodes": spec.n, "steps": args.steps, "config": ctx.config(),
                        "mass_drift_rel": abs(st["mass"] - spec.n * b.rho0) / (spec.n * b.rho0)}
@@ -128,59 +149,59 @@ def run_gpu(args, torch, gmf, wl):
         # plain FP64, same box
         w64 = wl.bandwidth_headline("fp64")
         s64 = max(10, args.steps // 5)
-        with gmf.Context([spec], precision=gmf.FP64, stream=stream, tune=args.tune) as ctx:
+        with gmf.Context([spec], precision=gmf.FP64, stream=stream, tune=args.tune, graph_steps=graph_len(s64)) as ctx:
             print(f"[bench] fp64 {w64.name}: steps {s64}", file=sys.stderr, flush=True)
-            sec = time_context(ctx, stream, s64, max(2, args.warmup // 5), torch)
+            sec = time_context(ctx, stream, s64, max(2, args.warmup // 5), torch, loops, "fp64")
             out["fp64"] = {"seconds": sec, "nodes": spec.n, "steps": s64, "config": ctx.config()}
         torch.cuda.synchronize()
         # batched ensemble
         we = wl.ensemble()
         specs = [gmf.ReplicaSpec(*bx.n, rho0=bx.rho0, tau=bx.tau, kbt=bx.kbt, seed=bx.seed) for bx in we.boxes]
         se = max(20, args.steps)
-        with gmf.Context(specs, precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune) as ctx:
+        with gmf.Context(specs, precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune,
+                         graph_steps=graph_len(se)) as ctx:
             print(f"[bench] batched {we.name}: steps {se}", file=sys.stderr, flush=True)
-            sec = time_context(ctx, stream, se, args.warmup, torch)
+            sec = time_context(ctx, stream, se, args.warmup, torch, loops, "batched")
             out["batched"] = {"seconds": sec, "nodes": we.nodes, "steps": se, "config": ctx.config(),
                               "workload": we.name}
         torch.cuda.synchronize()
         with gmf.Context(specs, precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune,
-                         storage=gmf.STORE_MOMENTS) as ctx:
+                         storage=gmf.STORE_MOMENTS, graph_steps=graph_len(se)) as ctx:
             print(f"[bench] batched {we.name}, moment storage: steps {se}", file=sys.stderr, flush=True)
-            sec = time_context(ctx, stream, se, args.warmup, torch)
+            sec = time_context(ctx, stream, se, args.warmup, torch, loops, "batched_mom")
             out["batched_mom"] = {"seconds": sec, "nodes": we.nodes, "steps": se, "config": ctx.config(),
                                   "workload": we.name}
         torch.cuda.synchronize()
         # the headline box with the in-place AA pattern (one population buffer: half the memory)
+        sa = max(20, args.steps // 4)
         with gmf.Context([spec], precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune,
-                         streaming=gmf.STREAM_AA) as ctx:
-            sa = max(20, args.steps // 4)
+                         streaming=gmf.STREAM_AA, graph_steps=graph_len(sa)) as ctx:
             print(f"[bench] fp32 AA streaming: steps {sa}", file=sys.stderr, flush=True)
-            sec = time_context(ctx, stream, sa, args.warmup, torch)
+            sec = time_context(ctx, stream, sa, args.warmup, torch, loops, "aa")
             out["aa"] = {"seconds": sec, "nodes": spec.n, "steps": sa, "config": ctx.config()}
         torch.cuda.synchronize()
         # the headline box with the fused sampler on (every 10 steps: variances and shell spectra)
+        ss = max(20, args.steps // 4) // 10 * 10
         with gmf.Context([spec], precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune,
-                         sample_every=10) as ctx:
-            ss = max(20, args.steps // 4)
+                         sample_every=10, graph_steps=graph_len(ss)) as ctx:
             print(f"[bench] fp32 sampled every 10: steps {ss}", file=sys.stderr, flush=True)
-            sec = time_context(ctx, stream, ss, 10, torch)
+            sec = time_context(ctx, stream, ss, 10, torch, loops, "sampled")
             out["sampled"] = {"seconds": sec, "nodes": spec.n, "steps": ss}
         torch.cuda.synchronize()
         # the headline box with the full-box shell spectra as well (FFT of six fields per sample)
         with gmf.Context([spec], precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune,
-                         sample_every=10, spectrum=1) as ctx:
-            ss = max(20, args.steps // 4)
+                         sample_every=10, spectrum=1, graph_steps=graph_len(ss)) as ctx:
             print(f"[bench] fp32 sampled every 10 with full spectra: steps {ss}", file=sys.stderr, flush=True)
-            sec = time_context(ctx, stream, ss, 10, torch)
+            sec = time_context(ctx, stream, ss, 10, torch, loops, "spectrum")
             out["spectrum"] = {"seconds": sec, "nodes": spec.n, "steps": ss}
         torch.cuda.synchronize()
         # the headline box in moment storage (ten moments per node), both precisions
         for prec, key, st in ((gmf.FP32_SHIFTED, "mom_fp32", max(20, args.steps // 4)),
                               (gmf.FP64, "mom_fp64", max(10, args.steps // 10))):
             with gmf.Context([spec], precision=prec, stream=stream, tune=args.tune,
-                             storage=gmf.STORE_MOMENTS) as ctx:
+                             storage=gmf.STORE_MOMENTS, graph_steps=graph_len(st)) as ctx:
                 print(f"[bench] {key} moment storage: steps {st}", file=sys.stderr, flush=True)
-                sec = time_context(ctx, stream, st, 4, torch)
+                sec = time_context(ctx, stream, st, 4, torch, loops, key)
                 out[key] = {"seconds": sec, "nodes": spec.n, "steps": st, "config": ctx.config()}
             torch.cuda.synchronize()
         print("[bench] variance accuracy: 64^3 tau sweep, FP32 batched vs FP64", file=sys.stderr, flush=True)
@@ -190,9 +211,9 @@ def run_gpu(args, torch, gmf, wl):
         bp = wp.boxes[0]
         sp = gmf.ReplicaSpec(*bp.n, rho0=bp.rho0, tau=bp.tau, kbt=bp.kbt, seed=bp.seed)
         for prec, key, st in ((gmf.FP32_SHIFTED, "fp32_512", 40), (gmf.FP64, "fp64_512", 20)):
-            with gmf.Context([sp], precision=prec, stream=stream, tune=args.tune) as ctx:
+            with gmf.Context([sp], precision=prec, stream=stream, tune=args.tune, graph_steps=graph_len(st)) as ctx:
                 print(f"[bench] {key}: steps {st}", file=sys.stderr, flush=True)
-                sec = time_context(ctx, stream, st, 4, torch)
+                sec = time_context(ctx, stream, st, 4, torch, loops, key)
                 out[key] = {"seconds": sec, "nodes": sp.n, "steps": st, "config": ctx.config()}
             torch.cuda.synchronize()
     return out
@@ -312,7 +333,8 @@ def make_line(args, res) -> dict:
     ms = rh["seconds"] / rh["steps"] * 1e3
     # roofline of the step kernel: algorithmic bytes per launch over its average
     # launch duration, i.e. the events around the timed region over its launches
-    # (the captured step loop launches the step kernel back to back)
+    # (the timed region is whole replays of graphs captured beforehand, which
+    # launch the step kernel back to back; "step_loop" records what ran)
     kernel_s = rh["seconds"] / rh["steps"]
     bpn = (MOM_BYTES_PER_NODE if args.storage == "moments" else BYTES_PER_NODE)[args.precision]
     achieved = bpn * rh["nodes"] / kernel_s / 1e9
@@ -346,6 +368,7 @@ def make_line(args, res) -> dict:
                                          rh["nodes"], rh["config"])},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "mass_drift_rel": rh["mass_drift_rel"],
+        "step_loop": res.get("step_loops", {}).get("headline"),
     }
     if "fp64" in res:
         r = res["fp64"]
@@ -421,6 +444,10 @@ def make_line(args, res) -> dict:
                     "traffic": profiled("mstep_fp32_256", r["nodes"], r["config"])}
     if "variance_accuracy" in res:
         line["variance_accuracy"] = res["variance_accuracy"]
+    # what each extra timed loop ran (graph replays, direct launches)
+    extra_loops = {k: v for k, v in res.get("step_loops", {}).items() if k != "headline"}
+    if extra_loops:
+        line["extra_step_loops"] = extra_loops
     return line
 
 

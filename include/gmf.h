@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define GMF_ABI_VERSION 1
+#define GMF_ABI_VERSION 2
 
 /* return codes */
 #define GMF_OK 0
@@ -70,7 +70,8 @@ extern "C" {
 #define GMF_ENOMEM (-2)     /* device or host allocation failed             */
 #define GMF_EDEVICE (-3)    /* a HIP call failed; the context is poisoned   */
 #define GMF_ESTATE (-4)     /* NULL context                                 */
-#define GMF_EUNSTABLE (-5)  /* a sampled density was NaN or infinite       */
+#define GMF_EUNSTABLE (-5)  /* a sampled density was NaN or infinite, or mass
+                               and momentum drifted past the bound (gmf_stats) */
 
 /* gmf_options.precision */
 #define GMF_FP64 0          /* populations f stored and stepped in FP64     */
@@ -145,7 +146,14 @@ typedef struct {
     int32_t collision;    /* GMF_COLLISION_GMF or GMF_COLLISION_BGK         */
     int32_t noise_rho;    /* 0: local rho in Eqs. (2)/(9); 1: rho0         */
     int32_t sample_every; /* > 0: sample f(., t) at every step with t % sample_every == 0; 0: off */
-    int32_t graph_steps;  /* steps per captured HIP graph; 0: direct launches; < 0: default (64) */
+    int32_t graph_steps;  /* longest run of steps captured in one HIP graph; 0: direct
+                             launches; < 0: the default (64).  A graph holds one
+                             sampling step or up to graph_steps non-sampling steps
+                             (between two samples closer than that, the run from one
+                             sample to the next); steps that fit no graph (the tail
+                             of a gmf_step call) are launched directly.  Graphs are
+                             captured on first use or by gmf_prepare; every choice
+                             gives the same bits. */
     int32_t tune;         /* 0: built-in kernel configuration; 1: time the variants at init */
     int32_t streaming;    /* GMF_STREAM_AUTO, GMF_STREAM_AB or GMF_STREAM_AA */
     int32_t spectrum;     /* 1: also accumulate the full-box shell spectra on every
@@ -167,6 +175,14 @@ typedef struct {
     double spectrum[GMF_NSPEC][GMF_NSHELL]; /* sum over samples of the shell average |m(k)|^2 */
     int32_t shell_n2[GMF_NSHELL];           /* |n|^2 of each shell          */
     int32_t shell_count[GMF_NSHELL];        /* integer vectors per shell    */
+    /* conservation guard (mass and momentum are invariants of Eqs. (1)/(10):
+     * the conserved modes k = 0..3 are neither relaxed nor noised) */
+    double mass_ref;                        /* reference mass (gmf_set_reference) */
+    double momentum_ref[3];                 /* reference momentum           */
+    double drift;                           /* max(|mass - mass_ref|, max_a |momentum_a -
+                                               momentum_ref_a|) / |mass_ref|  */
+    double drift_bound;                     /* 1e-10 (FP64), 1e-4 (FP32 shifted): above it
+                                               gmf_stats returns GMF_EUNSTABLE */
 } gmf_stats_t;
 
 /* Device bytes gmf_init needs when the caller provides the workspace.
@@ -202,6 +218,19 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt,
 /* Enqueue n >= 0 steps of Eq. (10) (or Eq. (1)) on every replica.  Asynchronous. */
 int gmf_step(gmf_ctx* ctx, int64_t n);
 
+/* Capture (without running anything) every HIP graph that gmf_step(ctx, n)
+ * from the current step would launch, so that the following gmf_step calls
+ * capture nothing: for timed regions and latency-bound loops.  n >= 0; a no-op
+ * with graph_steps = 0.  Capturing uses the context's stream; the graphs stay
+ * valid until gmf_destroy. */
+int gmf_prepare(gmf_ctx* ctx, int64_t n);
+
+/* What the step loop has launched since gmf_init: graph replays, the steps
+ * they covered, steps launched directly, and graphs captured so far.  Any
+ * output pointer may be NULL. */
+int gmf_get_launch_counts(gmf_ctx* ctx, int64_t* graph_launches, int64_t* graph_steps, int64_t* direct_steps,
+                          int32_t* graphs_captured);
+
 /* Density rho (N values) and velocity u = j/rho (3N values, ux | uy | uz) of
  * the current state of replica r, Eqs. (3)-(4), into caller-owned host
  * buffers (either may be NULL).  Synchronises. */
@@ -209,8 +238,18 @@ int gmf_moments(gmf_ctx* ctx, int32_t r, double* rho, double* u);
 
 /* Statistics of replica r: current FP64 mass and momentum, and the sums of the
  * sampled observables (see gmf_stats_t).  Synchronises.  Returns
- * GMF_EUNSTABLE (after filling *out) when a sampled density was not finite. */
+ * GMF_EUNSTABLE (after filling *out) when a sampled density was not finite,
+ * the mass is not finite, or drift exceeds drift_bound. */
 int gmf_stats(gmf_ctx* ctx, int32_t r, gmf_stats_t* out);
+
+/* Conservation reference of replica r that gmf_stats measures drift from.
+ * gmf_init takes the rest state's mass and momentum and gmf_set_populations
+ * the new state's, both as stored on the device.  ref = NULL: take the
+ * current state's (synchronises); else ref[0] = mass (finite, nonzero),
+ * ref[1..3] = momentum (finite), host array read during the call, e.g. the
+ * reference of the run a checkpoint was taken from, so that drift keeps
+ * counting across a resume.  GMF_EINVAL for r out of range or a bad ref. */
+int gmf_set_reference(gmf_ctx* ctx, int32_t r, const double* ref);
 
 /* Zero the sample accumulators of every replica (the full-box spectra too). */
 int gmf_reset_stats(gmf_ctx* ctx);
@@ -233,7 +272,8 @@ int gmf_spectrum(gmf_ctx* ctx, int32_t r, int32_t max_shells, double* sums, int6
 
 /* Canonical populations f(x, t) of replica r (27*N FP64 values, host). */
 int gmf_get_populations(gmf_ctx* ctx, int32_t r, double* f);
-/* Overwrite the state of replica r with f(x, t) (27*N FP64 values, host). */
+/* Overwrite the state of replica r with f(x, t) (27*N FP64 values, host), and
+ * take its mass and momentum as the new conservation reference. */
 int gmf_set_populations(gmf_ctx* ctx, int32_t r, const double* f);
 /* Canonical populations at `count` listed nodes (node indices 0 <= n < N, host
  * array) of replica r into f[27*j + i] (host).  Synchronises. */

@@ -43,7 +43,7 @@ EXPORTED = (
     "gmf_workspace_bytes", "gmf_init", "gmf_step", "gmf_moments", "gmf_stats", "gmf_reset_stats",
     "gmf_get_populations", "gmf_set_populations", "gmf_get_nodes", "gmf_get_step", "gmf_noise_probe",
     "gmf_get_config", "gmf_copy_probe", "gmf_destroy", "gmf_strerror", "gmf_spectrum", "gmf_get_tiling",
-    "gmf_get_occupancy",
+    "gmf_get_occupancy", "gmf_prepare", "gmf_get_launch_counts", "gmf_set_reference",
 )
 
 
@@ -64,7 +64,9 @@ class Stats(ctypes.Structure):
                 ("mass", ctypes.c_double), ("momentum", ctypes.c_double * 3),
                 ("sum_mean", ctypes.c_double * NOBS), ("sum_meansq", ctypes.c_double * NOBS),
                 ("sum_var", ctypes.c_double * NOBS), ("spectrum", (ctypes.c_double * NSHELL) * NSPEC),
-                ("shell_n2", ctypes.c_int32 * NSHELL), ("shell_count", ctypes.c_int32 * NSHELL)]
+                ("shell_n2", ctypes.c_int32 * NSHELL), ("shell_count", ctypes.c_int32 * NSHELL),
+                ("mass_ref", ctypes.c_double), ("momentum_ref", ctypes.c_double * 3),
+                ("drift", ctypes.c_double), ("drift_bound", ctypes.c_double)]
 
 
 class GmfError(RuntimeError):
@@ -95,6 +97,9 @@ def lib() -> ctypes.CDLL:
         L.gmf_init.argtypes = [ctypes.POINTER(Replica), ctypes.c_int32, ctypes.POINTER(Options), vp,
                                ctypes.c_size_t, vp, ctypes.POINTER(vp)]
         L.gmf_step.argtypes = [vp, ctypes.c_int64]
+        L.gmf_prepare.argtypes = [vp, ctypes.c_int64]
+        L.gmf_get_launch_counts.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int64)] * 3 + [ctypes.POINTER(ctypes.c_int32)]
+        L.gmf_set_reference.argtypes = [vp, ctypes.c_int32, dp]
         L.gmf_moments.argtypes = [vp, ctypes.c_int32, dp, dp]
         L.gmf_stats.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Stats)]
         L.gmf_reset_stats.argtypes = [vp]
@@ -117,7 +122,8 @@ def lib() -> ctypes.CDLL:
         L.gmf_strerror.restype = ctypes.c_char_p
         for name in ("gmf_init", "gmf_step", "gmf_moments", "gmf_stats", "gmf_reset_stats",
                      "gmf_get_populations", "gmf_set_populations", "gmf_get_nodes", "gmf_get_step",
-                     "gmf_noise_probe", "gmf_get_config", "gmf_spectrum", "gmf_get_tiling", "gmf_get_occupancy"):
+                     "gmf_noise_probe", "gmf_get_config", "gmf_spectrum", "gmf_get_tiling", "gmf_get_occupancy",
+                     "gmf_prepare", "gmf_get_launch_counts", "gmf_set_reference"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -246,6 +252,29 @@ class Context:
     def step(self, n: int = 1):
         _check(lib().gmf_step(self._h, int(n)), "gmf_step")
 
+    def prepare(self, n: int):
+        """Capture every graph that step(n) would launch, without running anything."""
+        _check(lib().gmf_prepare(self._h, int(n)), "gmf_prepare")
+
+    def launch_counts(self) -> dict:
+        g, gs, d = (ctypes.c_int64() for _ in range(3))
+        c = ctypes.c_int32()
+        _check(lib().gmf_get_launch_counts(self._h, ctypes.byref(g), ctypes.byref(gs), ctypes.byref(d),
+                                           ctypes.byref(c)), "gmf_get_launch_counts")
+        return {"graph_launches": g.value, "graph_steps": gs.value, "direct_steps": d.value,
+                "graphs_captured": c.value}
+
+    def set_reference(self, ref=None, r: int = 0):
+        """Conservation reference of replica r: None takes the current state's mass
+        and momentum, else (mass, mx, my, mz)."""
+        if ref is None:
+            _check(lib().gmf_set_reference(self._h, r, None), "gmf_set_reference")
+        else:
+            a = np.ascontiguousarray(ref, dtype=np.float64)
+            if a.size != 4:
+                raise ValueError("set_reference: (mass, mx, my, mz)")
+            _check(lib().gmf_set_reference(self._h, r, _dp(a)), "gmf_set_reference")
+
     @property
     def t(self) -> int:
         v = ctypes.c_int64()
@@ -293,6 +322,8 @@ class Context:
             "sum_var": np.array(s.sum_var[:]),
             "spectrum": np.array([list(row) for row in s.spectrum]),
             "shell_n2": np.array(s.shell_n2[:]), "shell_count": np.array(s.shell_count[:]),
+            "mass_ref": s.mass_ref, "momentum_ref": np.array(s.momentum_ref[:]),
+            "drift": s.drift, "drift_bound": s.drift_bound,
         }
 
     def reset_stats(self):

@@ -22,6 +22,7 @@
 #include "../../include/gmf.h"
 #include "gmf_device.hpp"
 #include "gmf_fft.hpp"
+#include "gmf_graphplan.hpp"
 #include "gmf_internal.hpp"
 
 using namespace gmf;
@@ -31,6 +32,13 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr size_t kStageCap = 64ull << 20;   // staging for host transfers (per chunk of z planes)
 constexpr int kDefaultGraphSteps = 64;
+// Conservation guard of gmf_stats: relative drift of mass and momentum from the
+// replica's reference (see conservation_drift) above which the call reports
+// GMF_EUNSTABLE, by precision (GMF_FP64, GMF_FP32_SHIFTED).  The update
+// conserves both exactly; rounding moves them by about 1e-16 (FP64) or 3e-9
+// (FP32, O(1e-2) shifted populations) per node and step, a random walk far
+// below these bounds for any run length a box can afford.
+constexpr double kDriftBound[2] = {1e-10, 1e-4};
 constexpr int kDefaultNpt = 1;
 constexpr float kTuneMargin = 0.01f;   // relative gain a later tuning candidate needs to win
 // workgroup mappings: linear, one contiguous range per XCD, runs of 16 blocks per XCD
@@ -313,11 +321,13 @@ struct gmf_ctx {
     int xcd_map = 0;               // workgroup mapping: 0 linear, else an index into kXcdChunks
     uint32_t occ = 0;              // population step: workgroups per CU cap (kOccCap; 0: none)
     uint32_t nblocks = 0;          // lattice grid for the current npt
-    int graph_steps = 0;           // 0: direct launches
-    int period = 2;                // step pattern period (A/B parity, sampling)
+    int graph_steps = 0;           // longest captured step loop; 0: direct launches
     int64_t step = 0;
     bool dev_step_valid = false;   // device counter == step
-    std::map<int, hipGraphExec_t> graphs;
+    std::map<int64_t, hipGraphExec_t> graphs;   // keyed by graph_key()
+    int64_t graph_launches = 0, graph_steps_run = 0, direct_steps = 0;
+    // conservation reference of each replica: mass and momentum[3] (FP64)
+    std::vector<std::array<double, 4>> ref;
     bool poisoned = false;
 
     void* pop(int which) { return ws + (which ? L.popB : L.popA); }
@@ -435,14 +445,18 @@ int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
     return GMF_OK;
 }
 
-int capture_graph(gmf_ctx* ctx, int phase, hipGraphExec_t* out)
+// Step loop in captured HIP graphs: which steps go into which graph is
+// decided by gmf_graphplan.hpp.
+GraphPlan graph_plan(const gmf_ctx* ctx) { return GraphPlan{ctx->opt.sample_every, ctx->graph_steps}; }
+
+int capture_graph(gmf_ctx* ctx, int64_t t, int64_t len, hipGraphExec_t* out)
 {
     hipGraph_t g = nullptr;
     CK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
     int rc = GMF_OK;
-    for (int j = 0; j < ctx->graph_steps && rc == GMF_OK; ++j) rc = enqueue_step(ctx, (int64_t)phase + j, true, j);
+    for (int j = 0; j < (int)len && rc == GMF_OK; ++j) rc = enqueue_step(ctx, t + j, true, j);
     if (rc == GMF_OK) {
-        hipError_t e = launch_advance_step(ctx->d_step(), ctx->graph_steps, ctx->stream);
+        hipError_t e = launch_advance_step(ctx->d_step(), len, ctx->stream);
         if (e != hipSuccess) rc = GMF_EDEVICE;
     }
     hipError_t e = hipStreamEndCapture(ctx->stream, &g);
@@ -462,34 +476,58 @@ int capture_graph(gmf_ctx* ctx, int phase, hipGraphExec_t* out)
     return GMF_OK;
 }
 
+// The graph for the unit at step t, captured on first use.
+int find_graph(gmf_ctx* ctx, int64_t t, int64_t len, bool sample, hipGraphExec_t* out)
+{
+    const int64_t key = graph_key(t, len, sample);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        hipGraphExec_t ex;
+        const int rc = capture_graph(ctx, t, len, &ex);
+        if (rc != GMF_OK) return rc;
+        it = ctx->graphs.emplace(key, ex).first;
+    }
+    *out = it->second;
+    return GMF_OK;
+}
+
 int run_steps(gmf_ctx* ctx, int64_t n)
 {
     while (n > 0) {
-        if (ctx->graph_steps > 0 && n >= ctx->graph_steps) {
-            const int phase = (int)(ctx->step % ctx->period);
-            auto it = ctx->graphs.find(phase);
-            if (it == ctx->graphs.end()) {
-                hipGraphExec_t ex;
-                int rc = capture_graph(ctx, phase, &ex);
-                if (rc != GMF_OK) return rc;
-                it = ctx->graphs.emplace(phase, ex).first;
-            }
+        bool sample = false;
+        const int64_t len = plan_unit(graph_plan(ctx), ctx->step, n, &sample);
+        if (len > 0) {
+            hipGraphExec_t ex;
+            int rc = find_graph(ctx, ctx->step, len, sample, &ex);
+            if (rc != GMF_OK) return rc;
             if (!ctx->dev_step_valid) {
                 CK(launch_set_step(ctx->d_step(), ctx->step, ctx->stream));
                 ctx->dev_step_valid = true;
             }
-            CK(hipGraphLaunch(it->second, ctx->stream));
-            ctx->step += ctx->graph_steps;
-            n -= ctx->graph_steps;
+            CK(hipGraphLaunch(ex, ctx->stream));
+            ctx->step += len;
+            n -= len;
+            ctx->graph_launches += 1;
+            ctx->graph_steps_run += len;
         } else {
             int rc = enqueue_step(ctx, ctx->step, false, 0);
             if (rc != GMF_OK) return rc;
             ctx->step += 1;
             n -= 1;
+            ctx->direct_steps += 1;
             ctx->dev_step_valid = false;
         }
     }
     return GMF_OK;
+}
+
+// Capture every graph that run_steps(n) from the current step would launch.
+int prepare_steps(gmf_ctx* ctx, int64_t n)
+{
+    return walk_graph_units(graph_plan(ctx), ctx->step, n, [&](int64_t t, int64_t len, bool sample) {
+        hipGraphExec_t ex;
+        return find_graph(ctx, t, len, sample, &ex);
+    });
 }
 
 // Storage layout of every replica for addressing mode m (0: plane-uniform with
@@ -754,6 +792,41 @@ uint32_t chunk_planes(const gmf_ctx* ctx, int r)
     return (uint32_t)std::min<uint64_t>(p, (uint64_t)ctx->reps[r].nz);
 }
 
+// FP64 mass and momentum of the current state of replica r (tot[0] = sum_x rho,
+// tot[1..3] = sum_x rho u), summed on the device over chunks of z planes.
+int device_totals(gmf_ctx* ctx, int r, double tot[4])
+{
+    const RepDev& R = ctx->rdev[r];
+    const uint64_t plane = (uint64_t)R.nx * R.ny;
+    const uint32_t cp = chunk_planes(ctx, r);
+    bool first = true;
+    for (uint32_t z0 = 0; z0 < R.nz; z0 += cp) {
+        const uint32_t z1 = std::min(R.nz, z0 + cp);
+        const uint64_t cnt = plane * (z1 - z0);
+        const uint32_t nb = (uint32_t)((cnt + kBlock - 1) / kBlock);
+        if (ctx->mom)
+            CK(launch_mmoments(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, nullptr, nullptr,
+                               ctx->d_mpart(), ctx->stream));
+        else
+            CK(launch_moments(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, nullptr, nullptr,
+                              ctx->d_mpart(), ctx->aa_odd(), ctx->stream));
+        CK(launch_sum_partials(ctx->d_mpart(), nb, ctx->d_tot(), first ? 0 : 1, ctx->stream));
+        first = false;
+    }
+    CK(hipMemcpyAsync(tot, ctx->d_tot(), sizeof(double) * 4, hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    return GMF_OK;
+}
+
+// Relative drift of mass and momentum from the reference:
+// max(|M - M_ref|, max_a |J_a - J_ref,a|) / |M_ref| (momentum per unit mass, a velocity).
+double conservation_drift(const double tot[4], const std::array<double, 4>& ref)
+{
+    double d = std::fabs(tot[0] - ref[0]);
+    for (int a = 1; a < 4; ++a) d = std::max(d, std::fabs(tot[a] - ref[a]));
+    return d / std::fabs(ref[0]);
+}
+
 int check_ctx(gmf_ctx* ctx)
 {
     if (!ctx) return GMF_ESTATE;
@@ -934,20 +1007,7 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
             return GMF_EDEVICE;
         }
     }
-    // graphs: K a multiple of the pattern period (A/B parity and the sampling cadence)
-    ctx->period = 2;
-    if (opt.sample_every > 0) {
-        int s = opt.sample_every, a = 2, b = s;
-        while (b) {
-            int t = a % b;
-            a = b;
-            b = t;
-        }
-        ctx->period = 2 / a * s;
-    }
-    int gs = opt.graph_steps < 0 ? kDefaultGraphSteps : opt.graph_steps;
-    if (gs > 0) gs = ((gs + ctx->period - 1) / ctx->period) * ctx->period;
-    ctx->graph_steps = gs;
+    ctx->graph_steps = opt.graph_steps < 0 ? kDefaultGraphSteps : opt.graph_steps;
 
     set_layout(ctx, ctx->mode);
     rc = build_grid(ctx, kDefaultNpt);
@@ -975,6 +1035,13 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
             return rc;
         }
     }
+    // conservation references of the rest state, as stored
+    ctx->ref.assign(nrep, std::array<double, 4>{0.0, 0.0, 0.0, 0.0});
+    for (int r = 0; r < nrep && rc == GMF_OK; ++r) rc = gmf_set_reference(ctx, r, nullptr);
+    if (rc != GMF_OK) {
+        gmf_destroy(ctx);
+        return rc;
+    }
     *out = ctx;
     return GMF_OK;
 }
@@ -986,6 +1053,26 @@ int gmf_step(gmf_ctx* ctx, int64_t n)
     if (n < 0) return GMF_EINVAL;
     DeviceGuard g(ctx->device);
     return run_steps(ctx, n);
+}
+
+int gmf_prepare(gmf_ctx* ctx, int64_t n)
+{
+    int rc = check_ctx(ctx);
+    if (rc != GMF_OK) return rc;
+    if (n < 0) return GMF_EINVAL;
+    DeviceGuard g(ctx->device);
+    return prepare_steps(ctx, n);
+}
+
+int gmf_get_launch_counts(gmf_ctx* ctx, int64_t* graph_launches, int64_t* graph_steps, int64_t* direct_steps,
+                          int32_t* graphs_captured)
+{
+    if (!ctx) return GMF_ESTATE;
+    if (graph_launches) *graph_launches = ctx->graph_launches;
+    if (graph_steps) *graph_steps = ctx->graph_steps_run;
+    if (direct_steps) *direct_steps = ctx->direct_steps;
+    if (graphs_captured) *graphs_captured = (int32_t)ctx->graphs.size();
+    return GMF_OK;
 }
 
 int gmf_moments(gmf_ctx* ctx, int32_t r, double* rho, double* u)
@@ -1024,26 +1111,10 @@ int gmf_stats(gmf_ctx* ctx, int32_t r, gmf_stats_t* out)
     if (rc != GMF_OK) return rc;
     if (r < 0 || r >= ctx->nrep || !out) return GMF_EINVAL;
     DeviceGuard g(ctx->device);
-    const RepDev& R = ctx->rdev[r];
-    const uint64_t plane = (uint64_t)R.nx * R.ny;
-    const uint32_t cp = chunk_planes(ctx, r);
-    bool first = true;
-    for (uint32_t z0 = 0; z0 < R.nz; z0 += cp) {
-        const uint32_t z1 = std::min(R.nz, z0 + cp);
-        const uint64_t cnt = plane * (z1 - z0);
-        const uint32_t nb = (uint32_t)((cnt + kBlock - 1) / kBlock);
-        if (ctx->mom)
-            CK(launch_mmoments(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, nullptr, nullptr,
-                               ctx->d_mpart(), ctx->stream));
-        else
-            CK(launch_moments(ctx->opt.precision, ctx->cur_pop(), ctx->d_reps() + r, R, z0, z1, nullptr, nullptr,
-                              ctx->d_mpart(), ctx->aa_odd(), ctx->stream));
-        CK(launch_sum_partials(ctx->d_mpart(), nb, ctx->d_tot(), first ? 0 : 1, ctx->stream));
-        first = false;
-    }
     double tot[4];
+    rc = device_totals(ctx, r, tot);
+    if (rc != GMF_OK) return rc;
     std::vector<double> acc(kAccStride);
-    CK(hipMemcpyAsync(tot, ctx->d_tot(), sizeof(tot), hipMemcpyDeviceToHost, ctx->stream));
     CK(hipMemcpyAsync(acc.data(), ctx->d_acc() + (size_t)r * kAccStride, sizeof(double) * kAccStride,
                       hipMemcpyDeviceToHost, ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
@@ -1064,7 +1135,33 @@ int gmf_stats(gmf_ctx* ctx, int32_t r, gmf_stats_t* out)
         out->shell_n2[s] = kShellN2[s];
         out->shell_count[s] = kShellCnt[s];
     }
-    if (out->nonfinite > 0 || !std::isfinite(out->mass)) return GMF_EUNSTABLE;
+    const std::array<double, 4>& ref = ctx->ref[r];
+    out->mass_ref = ref[0];
+    for (int a = 0; a < 3; ++a) out->momentum_ref[a] = ref[1 + a];
+    out->drift = conservation_drift(tot, ref);
+    out->drift_bound = kDriftBound[ctx->opt.precision];
+    // NaN drift (a non-finite total) fails the comparison and is caught below too
+    if (out->nonfinite > 0 || !std::isfinite(out->mass) || !(out->drift <= out->drift_bound)) return GMF_EUNSTABLE;
+    return GMF_OK;
+}
+
+int gmf_set_reference(gmf_ctx* ctx, int32_t r, const double* ref)
+{
+    int rc = check_ctx(ctx);
+    if (rc != GMF_OK) return rc;
+    if (r < 0 || r >= ctx->nrep) return GMF_EINVAL;
+    if (ref) {
+        if (!std::isfinite(ref[0]) || !(ref[0] != 0.0) || !std::isfinite(ref[1]) || !std::isfinite(ref[2]) ||
+            !std::isfinite(ref[3]))
+            return GMF_EINVAL;
+        for (int a = 0; a < 4; ++a) ctx->ref[r][a] = ref[a];
+        return GMF_OK;
+    }
+    DeviceGuard g(ctx->device);
+    double tot[4];
+    rc = device_totals(ctx, r, tot);
+    if (rc != GMF_OK) return rc;
+    for (int a = 0; a < 4; ++a) ctx->ref[r][a] = tot[a];
     return GMF_OK;
 }
 
@@ -1154,7 +1251,8 @@ int gmf_set_populations(gmf_ctx* ctx, int32_t r, const double* f)
                               ctx->stream));
         CK(hipStreamSynchronize(ctx->stream));
     }
-    return GMF_OK;
+    // the state as stored (rounded to the device precision) is the new conservation reference
+    return gmf_set_reference(ctx, r, nullptr);
 }
 
 int gmf_get_nodes(gmf_ctx* ctx, int32_t r, const int64_t* nodes, int32_t count, double* f)

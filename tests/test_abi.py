@@ -32,8 +32,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts():
     assert ctypes.sizeof(gmf.Replica) == 48
     assert ctypes.sizeof(gmf.Options) == 36
-    # 3 int64 + 4 doubles + 3*10 doubles + 40 doubles + 16 int32
-    assert ctypes.sizeof(gmf.Stats) == 8 * 3 + 8 * 4 + 8 * 30 + 8 * 40 + 4 * 16
+    # 3 int64 + 4 doubles + 3*10 doubles + 40 doubles + 16 int32 + the conservation guard's 6 doubles
+    assert ctypes.sizeof(gmf.Stats) == 8 * 3 + 8 * 4 + 8 * 30 + 8 * 40 + 4 * 16 + 8 * 6
 
 
 def _ws(specs, **kw):
@@ -109,5 +109,8 @@ def test_init_rejects_before_touching_the_device():
     assert lib.gmf_step(None, 1) == gmf.GMF_ESTATE
     assert lib.gmf_stats(None, 0, None) == gmf.GMF_ESTATE
     assert lib.gmf_get_occupancy(None, None) == gmf.GMF_ESTATE
+    assert lib.gmf_prepare(None, 1) == gmf.GMF_ESTATE
+    assert lib.gmf_get_launch_counts(None, None, None, None, None) == gmf.GMF_ESTATE
+    assert lib.gmf_set_reference(None, 0, None) == gmf.GMF_ESTATE
     assert lib.gmf_noise_probe(1, 0, 0, -1, 0, None, None) == gmf.GMF_EINVAL
     assert gmf.strerror(gmf.GMF_EUNSTABLE).startswith("non-finite")

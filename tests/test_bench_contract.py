@@ -90,3 +90,21 @@ def test_multi_gpu_request_exits_with_a_message():
     run = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "ensemble"],
                          capture_output=True, text=True, timeout=120)
     assert run.returncode == 2 and "--skip-extra" in run.stderr
+
+
+def test_timed_loops_are_whole_graph_replays():
+    """Every timed loop's graph length divides its step count, so the loop is
+    whole replays of graphs captured before timing (the driver's --steps 20
+    and the default 2000 included), and the line records what ran."""
+    for steps in (1, 7, 10, 20, 40, 200, 500, 2000, 4096):
+        g = bench.graph_len(steps)
+        assert 1 <= g <= 64 and steps % g == 0
+    assert bench.graph_len(20) == 20 and bench.graph_len(2000) == 50
+    res = _results()
+    res["step_loops"] = {"headline": {"steps_per_graph": 50, "graph_replays": 40, "graph_steps": 2000,
+                                      "direct_steps": 0, "captured_in_timed_region": 0},
+                         "fp64": {"steps_per_graph": 50, "graph_replays": 8, "graph_steps": 400,
+                                  "direct_steps": 0, "captured_in_timed_region": 0}}
+    line = bench.make_line(bench.parse_args([]), res)
+    assert line["step_loop"]["graph_steps"] == 2000 and line["step_loop"]["direct_steps"] == 0
+    assert line["extra_step_loops"]["fp64"]["graph_replays"] == 8

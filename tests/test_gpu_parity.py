@@ -339,3 +339,82 @@ def test_tune_cache(tmp_path, monkeypatch):
         assert runs[0][2] == 1 and runs[1][2] == 0, (runs[0][2], runs[1][2])   # timed once, then cached
         assert runs[0][0] == runs[1][0]
         assert np.array_equal(runs[0][1], runs[1][1])
+
+
+@pytest.mark.parametrize("precision", [gmf.FP64, gmf.FP32_SHIFTED])
+def test_conservation_guard(w, precision):
+    """gmf_stats measures mass and momentum drift from the replica's reference
+    (taken at init and at every set_populations, as stored) and reports
+    GMF_EUNSTABLE past the bound on a finite state.  The drift is forced
+    through set_populations: a second state with more mass replaces the first,
+    and the first state's reference is restored, as a resume of the first run
+    would do."""
+    spec = gmf.ReplicaSpec(12, 10, 9, 1.0, 0.7, 1e-4, 3)
+    say(f"conservation guard prec={precision}")
+    bound = 1e-10 if precision == gmf.FP64 else 1e-4
+    with gmf.Context([spec], precision=precision) as ctx:
+        st = ctx.stats()
+        assert st["drift"] == 0.0 and st["drift_bound"] == bound
+        assert abs(st["mass_ref"] - spec.n) < 1e-9 * spec.n
+        ctx.step(30)
+        st = ctx.stats()
+        assert st["drift"] < (1e-13 if precision == gmf.FP64 else 1e-6), st["drift"]
+        f0 = wl.perturbed_populations(w, spec.n, amp=0.05, seed=2, velocity=0.05)
+        ctx.set_populations(f0)
+        st0 = ctx.stats()
+        assert st0["drift"] == 0.0 and st0["mass_ref"] == st0["mass"]
+        assert np.array_equal(st0["momentum_ref"], st0["momentum"])
+        ref0 = np.array([st0["mass_ref"], *st0["momentum_ref"]])
+        ctx.step(20)
+        assert ctx.stats()["drift"] < (1e-13 if precision == gmf.FP64 else 1e-6)
+        # a state with 1% more mass: its own reference, so no drift ...
+        ctx.set_populations(1.01 * f0)
+        assert ctx.stats()["drift"] == 0.0
+        # ... until the first run's reference comes back
+        ctx.set_reference(ref0)
+        with pytest.raises(gmf.GmfError) as e:
+            ctx.stats()
+        assert e.value.code == gmf.GMF_EUNSTABLE
+        st = ctx.stats(allow_unstable=True)
+        assert st["nonfinite"] == 0 and np.isfinite(st["mass"])
+        assert abs(st["drift"] - 0.01) < 1e-3 and st["drift"] > bound
+        # re-baseline on the current state: stable again
+        ctx.set_reference()
+        assert ctx.stats()["drift"] == 0.0
+        # invalid references and replicas
+        for bad in ([0.0, 0, 0, 0], [np.nan, 0, 0, 0], [1.0, np.inf, 0, 0]):
+            with pytest.raises(gmf.GmfError) as e:
+                ctx.set_reference(bad)
+            assert e.value.code == gmf.GMF_EINVAL
+        with pytest.raises(gmf.GmfError) as e:
+            ctx.set_reference(None, r=1)
+        assert e.value.code == gmf.GMF_EINVAL
+
+
+@pytest.mark.parametrize("every,gs", [(3, 8), (0, 7), (100001, 64), (1, 4)])
+def test_prepare_captures_every_graph(every, gs):
+    """gmf_prepare captures every graph a run launches, so the run itself
+    captures none; graphs never exceed graph_steps steps, whatever the sampling
+    cadence (a very long odd cadence included); the trajectory and the
+    accumulators equal direct launches bit for bit."""
+    spec = gmf.ReplicaSpec(10, 8, 6, 1.0, 0.6, 1e-4, 8)
+    say(f"prepare sample_every={every} graph_steps={gs}")
+    out = []
+    for g in (0, gs):
+        with gmf.Context([spec], precision=gmf.FP32_SHIFTED, sample_every=every, graph_steps=g) as ctx:
+            ctx.step(5)
+            ctx.prepare(131)
+            before = ctx.launch_counts()
+            ctx.step(131)
+            after = ctx.launch_counts()
+            assert after["graphs_captured"] == before["graphs_captured"] <= 6
+            assert after["graph_steps"] + after["direct_steps"] == 136
+            if g:
+                assert after["graph_launches"] > 0
+                assert after["graph_steps"] - before["graph_steps"] <= g * (after["graph_launches"] - before["graph_launches"])
+            else:
+                assert after["graph_launches"] == 0 and after["graphs_captured"] == 0
+            st = ctx.stats()
+            out.append((ctx.get_populations(), st["sum_var"], st["spectrum"], st["nsamples"]))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
