@@ -291,6 +291,22 @@ int gmf_get_step(gmf_ctx* ctx, int64_t* t);
 int gmf_noise_probe(uint64_t seed, int64_t t, uint32_t node0, int32_t count, int32_t precision,
                     uint32_t* words, double* normals);
 
+/* gmf_noise_probe without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, latency-bound loops, harnesses that
+ * forbid hipMalloc).  Same outputs as gmf_noise_probe, bit for bit, staged in a
+ * fixed device array that the library holds on every device it runs on until
+ * the process ends (4.4 MiB per device; its address is looked up on the first
+ * call on each device).  The kernel and the copies to the host arrays run on
+ * hip_stream (NULL: the legacy stream), which is synchronised before return.
+ *   count  0 <= count <= GMF_PROBE_MAX_NODES, else GMF_EINVAL (nothing runs).
+ * Every call on one device shares that device's array: calls that overlap in
+ * time on one device (other threads or streams) race and must be serialised
+ * by the caller.  Nothing in the array needs clearing: each call writes every
+ * value it copies out. */
+#define GMF_PROBE_MAX_NODES 16384
+int gmf_noise_probe_noalloc(uint64_t seed, int64_t t, uint32_t node0, int32_t count, int32_t precision,
+                            uint32_t* words, double* normals, void* hip_stream);
+
 /* Kernel configuration in use (for reports): nodes per thread, threads per
  * workgroup, steps per captured HIP graph (0: direct launches), the
  * addressing mode of the step kernel (0: plane-uniform rows of 27 populations;

@@ -43,8 +43,9 @@ EXPORTED = (
     "gmf_workspace_bytes", "gmf_init", "gmf_step", "gmf_moments", "gmf_stats", "gmf_reset_stats",
     "gmf_get_populations", "gmf_set_populations", "gmf_get_nodes", "gmf_get_step", "gmf_noise_probe",
     "gmf_get_config", "gmf_copy_probe", "gmf_destroy", "gmf_strerror", "gmf_spectrum", "gmf_get_tiling",
-    "gmf_get_occupancy", "gmf_prepare", "gmf_get_launch_counts", "gmf_set_reference",
+    "gmf_get_occupancy", "gmf_prepare", "gmf_get_launch_counts", "gmf_set_reference", "gmf_noise_probe_noalloc",
 )
+PROBE_MAX_NODES = 16384
 
 
 class Replica(ctypes.Structure):
@@ -109,6 +110,8 @@ def lib() -> ctypes.CDLL:
         L.gmf_get_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         L.gmf_noise_probe.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32), dp]
+        L.gmf_noise_probe_noalloc.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32), dp, vp]
         L.gmf_get_config.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 6
         L.gmf_get_tiling.argtypes = [vp] + [ctypes.POINTER(ctypes.c_int32)] * 4
         L.gmf_get_occupancy.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
@@ -123,7 +126,7 @@ def lib() -> ctypes.CDLL:
         for name in ("gmf_init", "gmf_step", "gmf_moments", "gmf_stats", "gmf_reset_stats",
                      "gmf_get_populations", "gmf_set_populations", "gmf_get_nodes", "gmf_get_step",
                      "gmf_noise_probe", "gmf_get_config", "gmf_spectrum", "gmf_get_tiling", "gmf_get_occupancy",
-                     "gmf_prepare", "gmf_get_launch_counts", "gmf_set_reference"):
+                     "gmf_prepare", "gmf_get_launch_counts", "gmf_set_reference", "gmf_noise_probe_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -187,6 +190,18 @@ def noise_probe(seed: int, step: int, node0: int, count: int, precision: int = F
     rc = lib().gmf_noise_probe(seed, step, node0, count, precision,
                                words.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), _dp(normals))
     _check(rc, "gmf_noise_probe")
+    return words.reshape(count, 6, 4), normals.reshape(count, 23)
+
+
+def noise_probe_noalloc(seed: int, step: int, node0: int, count: int, precision: int = FP64, stream=None):
+    """noise_probe through the allocation-free entry point (at most PROBE_MAX_NODES
+    nodes; on a torch stream or the legacy stream)."""
+    words = np.zeros(24 * count, np.uint32)
+    normals = np.zeros(23 * count)
+    sp = None if stream is None else int(stream.cuda_stream)
+    rc = lib().gmf_noise_probe_noalloc(seed, step, node0, count, precision,
+                                       words.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), _dp(normals), sp)
+    _check(rc, "gmf_noise_probe_noalloc")
     return words.reshape(count, 6, 4), normals.reshape(count, 23)
 
 

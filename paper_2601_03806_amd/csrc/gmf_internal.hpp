@@ -123,6 +123,15 @@ hipError_t launch_nodes(int precision, const void* src, const RepDev* rep_dev, c
                         int32_t count, double* out, int aa_odd, hipStream_t s);
 hipError_t launch_noise_probe(int precision, uint64_t seed, int64_t t, uint32_t node0, int32_t count,
                               uint32_t* words, double* normals, hipStream_t s);
+// Fixed device scratch of the allocation-free noise probe (gmf_kernels.hip):
+// the words (24 per node) from offset 0 and the normals (23 doubles per node)
+// from kProbeNormalsOffset, for at most kProbeMaxNodes nodes per call.
+constexpr int32_t kProbeMaxNodes = 16384;
+constexpr size_t kProbeNormalsOffset = ((size_t)kProbeMaxNodes * 24 * sizeof(uint32_t) + 255) / 256 * 256;
+constexpr size_t kProbeScratchBytes = kProbeNormalsOffset + (size_t)kProbeMaxNodes * 23 * sizeof(double);
+// Device address of that scratch on the current device (each device holds its
+// own copy of the array at its own address).
+hipError_t probe_scratch_address(void** out);
 
 // moment storage: one step (tile: index into kMTileX/Y; a.tz planes per tile;
 // nblocks tiles in all, RepDev::block_begin/nblocks per replica), the rest state

@@ -946,6 +946,16 @@ __global__ __launch_bounds__(kBlock) void noise_probe_kernel(uint32_t k0, uint32
     }
 }
 
+// Staging of the allocation-free noise probe (gmf_noise_probe_noalloc): a
+// file-scope device array, so that the probe needs no device allocation.  Host
+// code never names it except to look up its address per device.
+static __device__ __align__(256) unsigned char scratch[kProbeScratchBytes];
+
+hipError_t probe_scratch_address(void** out)
+{
+    return hipGetSymbolAddress(out, HIP_SYMBOL(scratch));
+}
+
 hipError_t launch_noise_probe(int precision, uint64_t seed, int64_t t, uint32_t node0, int32_t count,
                               uint32_t* words, double* normals, hipStream_t s)
 {

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1355,6 +1356,62 @@ int gmf_noise_probe(uint64_t seed, int64_t t, uint32_t node0, int32_t count, int
     if (dn) (void)hipFree(dn);
     (void)hipStreamDestroy(s);
     return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Address of the allocation-free probe's device scratch, looked up once per
+// device (with that device current) and kept for the life of the process.
+constexpr int kMaxProbeDevices = 64;
+std::mutex g_probe_mu;
+void* g_probe_scratch[kMaxProbeDevices] = {};
+
+int probe_scratch(int dev, char** out)
+{
+    if (dev < 0 || dev >= kMaxProbeDevices) return GMF_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_probe_mu);
+    if (!g_probe_scratch[dev]) {
+        void* p = nullptr;
+        if (probe_scratch_address(&p) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return GMF_EDEVICE;
+        }
+        g_probe_scratch[dev] = p;
+    }
+    *out = static_cast<char*>(g_probe_scratch[dev]);
+    return GMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gmf_noise_probe_noalloc(uint64_t seed, int64_t t, uint32_t node0, int32_t count, int32_t precision,
+                            uint32_t* words, double* normals, void* hip_stream)
+{
+    if (count < 0 || count > kProbeMaxNodes || (precision != GMF_FP64 && precision != GMF_FP32_SHIFTED))
+        return GMF_EINVAL;
+    if ((uint64_t)node0 + (uint64_t)count > (1ull << 32)) return GMF_EINVAL;
+    if (count == 0 || (!words && !normals)) return GMF_OK;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return GMF_EDEVICE;
+    char* base = nullptr;
+    const int rc = probe_scratch(dev, &base);
+    if (rc != GMF_OK) return rc;
+    uint32_t* dw = words ? reinterpret_cast<uint32_t*>(base) : nullptr;
+    double* dn = normals ? reinterpret_cast<double*>(base + kProbeNormalsOffset) : nullptr;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (launch_noise_probe(precision, seed, t, node0, count, dw, dn, s) != hipSuccess) return GMF_EDEVICE;
+    if (words && hipMemcpyAsync(words, dw, sizeof(uint32_t) * 24 * (size_t)count, hipMemcpyDeviceToHost, s) !=
+                     hipSuccess)
+        return GMF_EDEVICE;
+    if (normals && hipMemcpyAsync(normals, dn, sizeof(double) * 23 * (size_t)count, hipMemcpyDeviceToHost, s) !=
+                       hipSuccess)
+        return GMF_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return GMF_EDEVICE;
+    return GMF_OK;
 }
 
 int gmf_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream)

@@ -113,4 +113,11 @@ def test_init_rejects_before_touching_the_device():
     assert lib.gmf_get_launch_counts(None, None, None, None, None) == gmf.GMF_ESTATE
     assert lib.gmf_set_reference(None, 0, None) == gmf.GMF_ESTATE
     assert lib.gmf_noise_probe(1, 0, 0, -1, 0, None, None) == gmf.GMF_EINVAL
+    # the allocation-free probe rejects sizes beyond its fixed scratch before any device call
+    assert gmf.PROBE_MAX_NODES == 16384
+    assert lib.gmf_noise_probe_noalloc(1, 0, 0, gmf.PROBE_MAX_NODES + 1, 0, None, None, None) == gmf.GMF_EINVAL
+    assert lib.gmf_noise_probe_noalloc(1, 0, 0, -1, 0, None, None, None) == gmf.GMF_EINVAL
+    assert lib.gmf_noise_probe_noalloc(1, 0, 0, 8, 7, None, None, None) == gmf.GMF_EINVAL
+    assert lib.gmf_noise_probe_noalloc(1, 0, 0xFFFFFFFF, 2, 0, None, None, None) == gmf.GMF_EINVAL
+    assert lib.gmf_noise_probe_noalloc(1, 0, 0, 0, 0, None, None, None) == gmf.GMF_OK
     assert gmf.strerror(gmf.GMF_EUNSTABLE).startswith("non-finite")
