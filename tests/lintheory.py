@@ -152,3 +152,94 @@ def shell_vectors(n2: int):
 def eig_closest(A: np.ndarray, target: complex):
     ev = np.linalg.eigvals(A)
     return ev[np.argmin(np.abs(ev - target))]
+
+
+def hydro_window_covariance(lat: Lattice, kvecs, tau, kbt, t_samples, rho0=1.0):
+    """Mean over the sample times t_samples of Sigma_h(k, t) = <h(k,t) h(k,t)^H>,
+    h = E[:10] f the ten hydrodynamic moments of the pre-collision state, for
+    the linearised GMF update started from rest (Sigma_h = 0 at t = 0).
+
+    GMF keeps no ghost content, so the ten moments are a closed linear
+    system: with T(k) = E[:10] S(k) W E^T B^-1 (10 x 27),
+        h(t+1) = T D h(t) + T xi(t),
+    D = diag(1, 1, 1, 1, (1-omega) x 6) on the ten moments, and xi the noise
+    of the modes k = 4..26 (variances of Eqs. (2), (9)).  Returns (nk, 10, 10)."""
+    kvecs = np.atleast_2d(np.asarray(kvecs, dtype=float))
+    om = 1.0 / tau
+    mu = rho0 * kbt / float(CS2)
+    var = np.zeros(27)
+    var[4:10] = mu * lat.b[4:10] * om * (2.0 - om)
+    var[10:] = mu * lat.b[10:]
+    back = (lat.w[:, None] * lat.E.T) / lat.b[None, :]               # W E^T B^-1 (27 x 27)
+    ph = np.exp(-1j * (kvecs @ lat.vel.T.astype(float)))             # (nk, 27)
+    T = lat.E[None, :10, :] * ph[:, None, :] @ back[None]             # (nk, 10, 27)
+    d10 = np.array([1.0] * 4 + [1.0 - om] * 6)
+    M = T[:, :, :10] * d10[None, None, :]
+    Qh = (T * var[None, None, :]) @ np.conj(np.transpose(T, (0, 2, 1)))
+    MH = np.conj(np.transpose(M, (0, 2, 1)))
+    ts = sorted(set(int(t) for t in t_samples))
+    want = set(ts)
+    Sig = np.zeros((len(kvecs), 10, 10), complex)
+    acc = np.zeros_like(Sig)
+    for t in range(1, ts[-1] + 1):
+        Sig = M @ Sig @ MH + Qh
+        if t in want:
+            acc += Sig
+    return acc / len(ts)                  # a sample at t = 0 (rest) adds Sigma_h = 0
+
+
+def signed_axis_map(rep, n):
+    """A 3x3 signed permutation G with G rep = n (rep and n integer 3-vectors
+    of equal sorted magnitudes)."""
+    rep = tuple(int(v) for v in rep)
+    n = tuple(int(v) for v in n)
+    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        G = np.zeros((3, 3), dtype=np.int64)
+        ok = True
+        for a in range(3):
+            src = rep[perm[a]]
+            if abs(src) != abs(n[a]):
+                ok = False
+                break
+            G[a, perm[a]] = -1 if (src != 0 and src == -n[a]) else 1
+        if ok:
+            assert tuple(G @ np.array(rep)) == n
+            return G
+    raise ValueError(f"{n} is not a signed permutation of {rep}")
+
+
+def shell_powers(lat: Lattice, L: int, shells, tau, kbt, t_samples, rho0=1.0):
+    """Linear-theory shell spectra averaged over the sample times: for each
+    shell (a list of integer wave vectors n of a cubic box of side L) the mean
+    over its vectors of <|m(k)|^2>, orthonormal DFT, for the spectra
+    rho, j (mean of the three components), sum_a j_a, sum_a Pi_aa and
+    sum_{a<b} Pi_ab.  Returns an array (5, len(shells)).
+
+    The lattice and the linearised update are invariant under the 48 signed
+    axis permutations g, so Sigma(g k) is Sigma(k) with the velocities
+    relabelled (c -> g c): an observable v at g k has the power of v(g c) at
+    k.  The recursion runs once per orbit representative (|n_x| >= |n_y| >=
+    |n_z| >= 0)."""
+    vel = lat.vel
+    index = {tuple(int(x) for x in c): i for i, c in enumerate(vel)}
+    obs = lat.obs_vectors()
+    names = ("rho", "jx", "jy", "jz", "jsum", "pdiag", "poff")
+    reps = sorted({tuple(sorted((abs(int(a)) for a in n), reverse=True)) for sh in shells for n in sh})
+    Sh = hydro_window_covariance(lat, [kvec_of(r, (L, L, L)) for r in reps], tau, kbt, t_samples, rho0)
+    rep_index = {r: i for i, r in enumerate(reps)}
+    out = np.zeros((5, len(shells)))
+    for s, sh in enumerate(shells):
+        acc = np.zeros(5)
+        for n in sh:
+            r = tuple(sorted((abs(int(a)) for a in n), reverse=True))
+            G = signed_axis_map(r, n)
+            perm = np.array([index[tuple(int(x) for x in G @ c)] for c in vel])   # i -> index of G c_i
+            S = Sh[rep_index[r]]
+            pw = {}
+            for name in names:
+                vg = obs[name][perm]                                  # v(G c_i)
+                alpha = (lat.E[:10] @ (lat.w * vg)) / lat.b[:10]      # Hermite coefficients of v(G c)
+                pw[name] = float(np.real(alpha @ S @ alpha))
+            acc += [pw["rho"], (pw["jx"] + pw["jy"] + pw["jz"]) / 3, pw["jsum"], pw["pdiag"], pw["poff"]]
+        out[:, s] = acc / len(sh)
+    return out

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
+import lintheory as lt
 import paper_2601_03806_amd as gmf
 from paper_2601_03806_amd import workloads as wl
 from gpu_common import oracle_params, rel_err, say
@@ -274,50 +275,163 @@ def test_largest_box_1024cube_aa_with_sampling(tabs):
     assert s1["nsamples"] == 3 and np.isfinite(s1["sum_var"]).all() and s1["sum_var"][0] > 0
 
 
+def nonlinear_allowance(tau, kbt, rho0=1.0):
+    """Allowance for the second-order excess that the linear target leaves out.
+    The equilibrium stress rho u_a u_b (of order k_BT per component) enters
+    every collision with weight omega (Eq. (10): a2* = omega rho u u + (1 - omega) a2)
+    and persists with memory (1 - omega)^2 per step, which adds
+    omega^2 k_BT^2 / (omega (2 - omega)) to each off-diagonal stress variance
+    rho0 k_BT / 3: a relative excess of 3 omega k_BT / ((2 - omega) rho0)
+    (1.5% at tau 0.51, 0.15% at tau 0.6, 0.03% at tau 1, for k_BT = 1e-4).
+    Twice that is allowed."""
+    om = 1.0 / tau
+    return 6.0 * om * kbt / ((2.0 - om) * rho0)
+
+
 @pytest.mark.slow
-@pytest.mark.parametrize("storage", [gmf.STORE_POPULATIONS, gmf.STORE_MOMENTS])
-def test_spectral_equilibration_256cube(storage):
-    """The Results-section measurement on the headline lattice: 256^3, k_BT 1e-4,
-    GMF-FLBM in FP32 (population and moment storage), tau in {0.6, 1, 5}
-    batched in one context, 8000 warm-up
-    steps, then 10000 steps with the full-box spectra sampled every 10.  The
-    spectral ER_m(|k|) = S_m(|k|) / S_m^theory over the shells |k| = 4..64
-    (integer |n|): its mean over the shells is within 1% of 1, and its mean over
-    each octave band (4-7, 8-15, 16-31, 32-64) within 2% plus four standard
-    errors of that band.  The standard error is estimated from the decay of the
-    slow modes: a mode of wavenumber k relaxes at about nu k^2 (shear and, with
-    the bulk viscosity of a single relaxation time, sound alike), so the time
-    mean of its power over T steps has relative variance 1 / (nu k^2 T), and no
-    less than 1 / n_samples; k and -k are one mode of a real field.  At tau 0.6
-    this error is 1.4% for the lowest band and below 0.3% above it, so single
-    small shells (a few percent each) are not tested."""
-    kbt = 1e-4
-    taus = (0.6, 1.0, 5.0)
-    specs = [gmf.ReplicaSpec(256, 256, 256, 1.0, t, kbt, 11 + i) for i, t in enumerate(taus)]
-    flat = np.array([kbt / CS2, kbt, 3 * kbt, 5 * kbt, kbt])[:, None]
-    names = ("rho", "j", "jsum", "pdiag", "poff")
-    say(f"spectral ER at 256^3, storage {storage}")
-    with gmf.Context(specs, precision=gmf.FP32_SHIFTED, sample_every=10, spectrum=1, storage=storage) as ctx:
-        ctx.step(8000)
+def test_small_tau_shell_spectra_vs_finite_time_theory(tabs):
+    """The 64^3 tau-sweep measurement at the two smallest viscosities, where the
+    small shells are far from equilibrium within the window: FP32 shifted,
+    64 seeds per case in one batched context (tau 0.51 and 0.6 at k_BT 1e-4,
+    and tau 0.51 at k_BT 1e-5), 2000 warm-up + 20000 steps sampled every 10.
+    For each of the 8 smallest shells (|n|^2 = 1, 2, 3, 4, 5, 6, 8, 9) and the
+    five spectra (Results section, Eqs. (14)-(16)), the mean over the seeds of
+    S_m(k) divided by the finite-time linear target, i.e. the exact covariance
+    recursion of the linearised update from rest averaged over the same sample
+    times (tests/lintheory.py), lies within 4.5 standard errors measured from
+    the seed-to-seed spread plus the second-order allowance.  The smallest
+    shell's target is 0.505 of the equilibrium value at tau 0.51, so the test
+    sees the slow approach to equilibrium, not only the end state; a batch-means
+    error of one run cannot be used here, since the slowest modes decorrelate
+    over 1 / (nu k^2) = 31000 steps, longer than the window.  These wave numbers
+    are those of the shells |n| = 4..12 of a 256^3 box.  The off-diagonal stress
+    exceeds the linear target at tau 0.51 by the second-order effect that the
+    allowance bounds; with k_BT ten times smaller that excess is at least five
+    times smaller (it is second order in the fluctuations)."""
+    vel = tabs[0]
+    lat = lt.Lattice(vel)
+    cases = ((0.51, 1e-4), (0.6, 1e-4), (0.51, 1e-5))
+    seeds = 64
+    specs = [gmf.ReplicaSpec(64, 64, 64, 1.0, tau, kbt, 5000 * (c + 1) + s)
+             for c, (tau, kbt) in enumerate(cases) for s in range(seeds)]
+    w = wl.tau_sweep("fp32")
+    say(f"small-tau shell spectra: {len(specs)} replicas of 64^3, {w.warmup} + {w.steps} steps")
+    with gmf.Context(specs, precision=gmf.FP32_SHIFTED, sample_every=w.sample_every) as ctx:
+        ctx.step(w.warmup)
         ctx.reset_stats()
-        ctx.step(10000)
-        for r, t in enumerate(taus):
+        ctx.step(w.steps)
+        st = [ctx.stats(r) for r in range(len(specs))]
+    ts = list(range(w.warmup, w.warmup + w.steps, w.sample_every))
+    shells = [lt.shell_vectors(n2) for n2 in (1, 2, 3, 4, 5, 6, 8, 9)]
+    names = ("rho", "j", "jsum", "pdiag", "poff")
+    poff_excess = {}
+    for c, (tau, kbt) in enumerate(cases):
+        assert all(x["nsamples"] == len(ts) for x in st[c * seeds:(c + 1) * seeds])
+        S = np.array([x["spectrum"] / x["nsamples"] for x in st[c * seeds:(c + 1) * seeds]])   # (seeds, 5, 8)
+        target = lt.shell_powers(lat, 64, shells, tau, kbt, ts)
+        ratio = S / target[None]
+        mean = ratio.mean(axis=0)
+        se = ratio.std(axis=0, ddof=1) / np.sqrt(seeds)
+        flat = np.array([kbt / CS2, kbt, 3 * kbt, 5 * kbt, kbt])[:, None]
+        allow = nonlinear_allowance(tau, kbt)
+        say(f"  tau {tau}, k_BT {kbt}: target / equilibrium on the smallest shell "
+            + " ".join(f"{names[m]} {target[m, 0] / flat[m, 0]:.3f}" for m in range(5)))
+        for m in range(5):
+            say(f"    {names[m]:5s} mean/target " + " ".join(f"{v:.4f}" for v in mean[m]) +
+                "   se " + " ".join(f"{v:.4f}" for v in se[m]))
+        dev = np.abs(mean - 1.0)
+        assert np.all(dev < 4.5 * se + allow), (tau, kbt, mean, se, allow)
+        poff_excess[(tau, kbt)] = float(mean[4].mean() - 1.0)
+        if tau == 0.51:
+            assert target[0, 0] / flat[0, 0] < 0.6          # far from equilibrium: the finite-time target matters
+    say(f"  off-diagonal stress excess over the linear target: {poff_excess}")
+    assert poff_excess[(0.51, 1e-5)] < poff_excess[(0.51, 1e-4)] / 5
+
+
+def _rounded_shell(s):
+    """Integer vectors n with s - 1/2 <= |n| < s + 1/2 (all |n_a| <= s + 1 < L/2)."""
+    r = s + 1
+    return [(a, b, c) for a in range(-r, r + 1) for b in range(-r, r + 1) for c in range(-r, r + 1)
+            if (2 * s - 1) ** 2 <= 4 * (a * a + b * b + c * c) < (2 * s + 1) ** 2]
+
+
+SPEC256 = {"kbt": 1e-4, "warm": 3000, "steps": 8000, "every": 10, "bands": ((4, 8), (8, 16), (16, 32), (32, 65))}
+
+
+def _spectra_256(boxes, storage):
+    """Sampled full-box shell spectra (sums / samples, (boxes, 5, nshell)) and
+    shell counts of 256^3 boxes run together for the SPEC256 window."""
+    warm, steps, every = SPEC256["warm"], SPEC256["steps"], SPEC256["every"]
+    say(f"spectral ER at 256^3, storage {storage}, {len(boxes)} boxes")
+    out = []
+    with gmf.Context(boxes, precision=gmf.FP32_SHIFTED, sample_every=every, spectrum=1, storage=storage) as ctx:
+        for k in range(0, warm + steps, 1000):
+            if k == warm:
+                ctx.reset_stats()
+            ctx.step(1000)
+            ctx.stats(0)                                              # synchronise: progress is real
+            say(f"  step {k + 1000} of {warm + steps}")
+        for r in range(len(boxes)):
             ns = ctx.stats(r)["nsamples"]
+            assert ns == steps // every
             sums, cnt = ctx.spectrum(r)
-            er = sums[:, 4:65] / ns / flat
-            say(f"  tau={t}: ER min/max " + "  ".join(f"{names[m]} {er[m].min():.3f}/{er[m].max():.3f}" for m in range(5)) +
-                "; mean " + " ".join(f"{v:.4f}" for v in er.mean(axis=1)))
-            say("    rho ER by shell 4..12: " + " ".join(f"{v:.3f}" for v in er[0, :9]))
-            assert ns == 1000
-            assert np.all(np.abs(er.mean(axis=1) - 1) < 0.01), (t, er.mean(axis=1))
-            nu = (t - 0.5) * CS2
-            c = cnt[4:65]
-            shells = np.arange(4, 65)
-            k2 = (2 * np.pi * shells / 256) ** 2
-            rel_var = np.maximum(1.0 / (nu * k2 * 10000), 1.0 / ns)
-            for lo, hi in ((4, 8), (8, 16), (16, 32), (32, 65)):
-                sel = slice(lo - 4, hi - 4)
-                band = (er[:, sel] * c[sel]).sum(axis=1) / c[sel].sum()
-                sigma = np.sqrt(np.sum(2 * rel_var[sel] * c[sel])) / c[sel].sum()
-                say(f"    band {lo}-{hi - 1}: " + " ".join(f"{v:.4f}" for v in band) + f"  (standard error {sigma:.4f})")
-                assert np.all(np.abs(band - 1) < 0.02 + 4 * sigma), (t, lo, hi, band, sigma)
+            out.append(sums / ns)
+    return np.array(out), cnt
+
+
+def _band_er_256(tabs, spectra, cnt, tau):
+    """Band-averaged ER of each box against the finite-time linear target:
+    the exact covariance recursion from rest averaged over the sample times on
+    shells 4..8, the equilibrium value beyond (within 2e-4 of it there).
+    Returns (boxes, 5 spectra, 4 bands)."""
+    kbt = SPEC256["kbt"]
+    flat = np.array([kbt / CS2, kbt, 3 * kbt, 5 * kbt, kbt])[:, None]
+    shells = [_rounded_shell(s) for s in range(4, 9)]
+    assert [len(v) for v in shells] == list(cnt[4:9])
+    ts = list(range(SPEC256["warm"], SPEC256["warm"] + SPEC256["steps"], SPEC256["every"]))
+    ft = lt.shell_powers(lt.Lattice(tabs[0]), 256, shells, tau, kbt, ts)
+    assert np.all(np.abs(ft[:, -1] / flat[:, 0] - 1) < 2e-4)         # shell 8 and beyond: equilibrated
+    target = np.repeat(flat, 65, axis=1)
+    target[:, 4:9] = ft
+    er = spectra[:, :, :65] / target[None]
+    return np.stack([(er[:, :, lo:hi] * cnt[lo:hi]).sum(axis=2) / cnt[lo:hi].sum() for lo, hi in SPEC256["bands"]],
+                    axis=2)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("tau", [0.6, 1.0])
+def test_spectral_equilibration_256cube(tabs, tau):
+    """The Results-section measurement on the headline lattice: 256^3, k_BT
+    1e-4, GMF-FLBM in FP32, eight seeds batched in one context; 3000 warm-up
+    steps, then 8000 steps with the full-box spectra sampled every 10.  The
+    spectral ER_m(|k|) = S_m(|k|) / S_m^target over the shells |k| = 4..64
+    (integer |n|), averaged per octave band (4-7, 8-15, 16-31, 32-64) with the
+    shell counts as weights, against the finite-time linear target.  The mean
+    over the eight seeds lies within 5 standard errors measured from their
+    spread plus the second-order allowance.  The 64^3 test above measures the
+    band 4..7 wave numbers with 64 seeds."""
+    seeds = 8
+    names = ("rho", "j", "jsum", "pdiag", "poff")
+    specs = [gmf.ReplicaSpec(256, 256, 256, 1.0, tau, SPEC256["kbt"], 11 + int(tau * 100) + s) for s in range(seeds)]
+    spectra, cnt = _spectra_256(specs, gmf.STORE_POPULATIONS)
+    be = _band_er_256(tabs, spectra, cnt, tau)
+    mean = be.mean(axis=0)
+    se = be.std(axis=0, ddof=1) / np.sqrt(seeds)
+    allow = nonlinear_allowance(tau, SPEC256["kbt"])
+    for b, (lo, hi) in enumerate(SPEC256["bands"]):
+        say(f"  tau {tau} band {lo}-{hi - 1}: " +
+            " ".join(f"{names[m]} {mean[m, b]:.4f}+-{se[m, b]:.4f}" for m in range(5)))
+    assert np.all(np.abs(mean - 1) < 5 * se + allow), (tau, mean, se, allow)
+
+
+@pytest.mark.slow
+def test_moment_storage_spectra_256cube(tabs):
+    """Moment storage reproduces the 256^3 spectra of population storage: two
+    seeds at tau 0.6 run in both storages with the same noise give band ER
+    values within 0.2% of each other."""
+    specs = [gmf.ReplicaSpec(256, 256, 256, 1.0, 0.6, SPEC256["kbt"], 71 + s) for s in range(2)]
+    pop, cnt = _spectra_256(specs, gmf.STORE_POPULATIONS)
+    mom, _ = _spectra_256(specs, gmf.STORE_MOMENTS)
+    ratio = _band_er_256(tabs, mom, cnt, 0.6) / _band_er_256(tabs, pop, cnt, 0.6)
+    say("  moment / population storage, band ER: " + " ".join(f"{v:.5f}" for v in ratio.ravel()))
+    assert np.all(np.abs(ratio - 1) < 2e-3), ratio
