@@ -195,9 +195,9 @@ typedef struct {
  *   storage group of 27, 3 or 1 populations over the whole replica within
  *   32-bit byte offsets (at the least nx*ny*nz*element bytes < 4 GiB), or
  *   every z plane a whole number of 256-node workgroups;
- *   with sampling: at most 2^16 spectrum work chunks per replica (nz planes,
- *   taken 256/nx at a time when nx <= 256) and sum(6 * 28 * nz) < 2^32 over
- *   the replicas;
+ *   with sampling: 6 * 28 * nz * ceil(nx / 64) summed over the replicas
+ *   (the partial sums of the first DFT stage, per plane and block of 64
+ *   columns; one block for nx < 64) below 2^32;
  *   with full-box spectra: nx, ny, nz <= 1024 with prime factors 2, 3, 5. */
 size_t gmf_workspace_bytes(const gmf_replica* reps, int32_t nrep, const gmf_options* opt);
 

@@ -165,7 +165,9 @@ __device__ __forceinline__ RepDev uniform_rep(const RepDev& in)
     R.grp_elems = sgpr64(in.grp_elems);
     R.row_stride = sgpr(in.row_stride);
     R.tw_offset = sgpr(in.tw_offset);
-    R.obs_chunks = sgpr(in.obs_chunks);
+    R.slice_first = sgpr(in.slice_first);
+    R.obs_first = sgpr(in.obs_first);
+    R.obs_blocks = sgpr(in.obs_blocks);
     R.pad2 = 0;
     R.rho0 = sgprf(in.rho0);
     R.omega = sgprf(in.omega);
@@ -244,10 +246,14 @@ __device__ __forceinline__ void add_noise(const RepDev& R, T sr, const T r[23], 
 }
 
 // Workgroup sums of NV doubles (kBlock threads), written by threads 0..NV-1.
-template <int NV>
-__device__ __forceinline__ void block_sum_store(double (&v)[NV], double* out)
+// Sums of NV doubles over the NT threads of a workgroup (NT a multiple of 64),
+// in a fixed order (butterfly within each wave, then the waves in turn):
+// threads 0 .. NV - 1 store them to out.  Every thread must call it.
+template <int NV, int NT>
+__device__ __forceinline__ void block_sum_store_nt(double (&v)[NV], double* out)
 {
-    __shared__ double red[kBlock / 64][NV];
+    static_assert(NT % 64 == 0, "whole wavefronts");
+    __shared__ double red[NT / 64][NV];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -264,9 +270,45 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* out)
     if (threadIdx.x < NV) {
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+        for (int w = 0; w < NT / 64; ++w) s += red[w][threadIdx.x];
         out[threadIdx.x] = s;
     }
+}
+
+// Observables of one sampled node, from the six sampled fields in the kernel
+// precision (rho - rho0, j, sum_a Pi_aa - 3 rho0 cs2, sum_{a<b} Pi_ab; the
+// order of gmf.h's GMF_OBS_*), added in FP64 to a partial record: the sums of
+// o and o^2 and the count of non-finite densities.  u = j / rho is formed in
+// the kernel precision (the fields carry no more), everything after in FP64.
+constexpr int kObsVals = 2 * kObs + 1;
+template <typename T>
+__device__ __forceinline__ void add_observables(double (&acc)[kObsVals], T rho0, T drho, T jx, T jy, T jz,
+                                                T pdiag, T poff)
+{
+    const T irho = recip(rho0 + drho);
+    double o[kObs];
+    o[0] = (double)drho;
+    o[1] = (double)jx;
+    o[2] = (double)jy;
+    o[3] = (double)jz;
+    o[4] = o[1] + o[2] + o[3];
+    o[5] = (double)pdiag;
+    o[6] = (double)poff;
+    o[7] = (double)(jx * irho);
+    o[8] = (double)(jy * irho);
+    o[9] = (double)(jz * irho);
+#pragma unroll
+    for (int q = 0; q < kObs; ++q) {
+        acc[2 * q] += o[q];
+        acc[2 * q + 1] = fma(o[q], o[q], acc[2 * q + 1]);
+    }
+    acc[2 * kObs] += isfinite(o[0]) ? 0.0 : 1.0;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], double* out)
+{
+    block_sum_store_nt<NV, kBlock>(v, out);
 }
 
 }  // namespace gmf

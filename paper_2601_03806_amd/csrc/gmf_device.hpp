@@ -30,7 +30,8 @@ namespace gmf {
 constexpr int Q = 27;
 constexpr int kBlock = 256;          // threads per workgroup of the lattice kernels
 constexpr int kObs = 10;             // sampled observables (see gmf.h)
-constexpr int kPartialStride = 24;   // doubles per workgroup partial record (2*kObs + 1, padded)
+constexpr int kPartialStride = 24;   // doubles per partial record of the observables (2*kObs + 1, padded)
+constexpr uint32_t kObsNodes = 16 * kBlock;   // nodes per workgroup of the observables kernel (16 per thread)
 constexpr int kFields = 6;           // fields kept for the spectra: drho, jx, jy, jz, pdiag, poff
 constexpr int kDftNx = 4;            // n_x = 0..3 in the first DFT stage
 constexpr int kDftNy = 7;            // n_y = -3..3
@@ -38,7 +39,6 @@ constexpr int kDftPlane = kDftNx * kDftNy;
 constexpr int kShells = 8;
 constexpr int kSpec = 5;
 constexpr int kAccStride = 3 * kObs + kSpec * kShells + 8;  // doubles per replica accumulator
-constexpr int kObsChunks = 1024;     // most workgroups per replica in the observables reduction
 constexpr int kZSplit = 16;          // z chunks of the third DFT stage
 
 __host__ __device__ constexpr int tcx(int p) { return p / 9 - 1; }
@@ -89,7 +89,9 @@ struct RepDev {
     uint64_t grp_elems;       // elements per storage group (n * grp)
     uint32_t row_stride;      // elements between consecutive rows of a group (grp * nx)
     uint32_t tw_offset;       // offset (complex values) of the replica's twiddle tables (nx, ny, nz entries)
-    uint32_t obs_chunks;      // workgroups of the observables reduction (<= kObsChunks)
+    uint32_t slice_first;     // first slice record of the replica in the statistics reduction
+    uint32_t obs_first;       // first workgroup (and partial record) of the replica in observables_kernel
+    uint32_t obs_blocks;      // its workgroups there: ceil(n / kObsNodes)
     uint32_t pad2;
     double rho0;
     double omega;             // 1 / tau
@@ -99,7 +101,7 @@ struct RepDev {
     float rho0f, omegaf, one_m_omegaf, padf;
     float ampf[8];
     // full-box spectra (only when they are switched on)
-    uint64_t spec_offset;     // complex offset of the replica's three packed field transforms (3 N values)
+    uint64_t spec_offset;     // offset (complex values of the kernel precision) of the replica's seven half spectra
     uint32_t shell_offset;    // first shell record of the replica
     uint32_t nshell;          // shells 0 .. nshell - 1 (shell 0 holds k = 0 only and stays empty)
 };
@@ -113,9 +115,31 @@ __host__ __device__ inline double rep_param<double>(double d, float) { return d;
 template <>
 __host__ __device__ inline float rep_param<float>(double, float f) { return f; }
 
-// Planes per workgroup of the first shell-spectrum DFT stage: kBlock / nx for
-// nx <= kBlock (one column per thread), else 1 (threads loop over columns).
-__host__ __device__ inline uint32_t dft_planes_per_block(uint32_t nx) { return nx <= (uint32_t)kBlock ? kBlock / nx : 1u; }
+// Work units ("chunks") of the first shell-spectrum DFT stage: 64 columns
+// (x, z) of the box, one per lane of a wavefront.  nx >= 64: a block of 64
+// columns of one z plane, ceil(nx / 64) blocks per plane; nx < 64: floor(64 / nx)
+// whole planes (one block per plane).  Partial records are kept per plane and
+// column block.
+constexpr uint32_t kDftCols = 64;
+__host__ __device__ inline uint32_t dft_col_blocks(uint32_t nx) { return nx >= kDftCols ? (nx + kDftCols - 1) / kDftCols : 1u; }
+__host__ __device__ inline uint32_t dft_planes_per_chunk(uint32_t nx) { return nx >= kDftCols ? 1u : kDftCols / nx; }
+__host__ __device__ inline uint64_t dft_chunks(uint32_t nx, uint32_t nz)
+{
+    return nx >= kDftCols ? (uint64_t)nz * dft_col_blocks(nx) : ((uint64_t)nz + dft_planes_per_chunk(nx) - 1) / dft_planes_per_chunk(nx);
+}
+
+// Replica of workgroup b of a grid laid out by the prefix array first
+// (first[r] <= b < first[r + 1], first[0] = 0).
+__device__ __forceinline__ int replica_of_block(const uint32_t* first, int32_t nrep, uint32_t b)
+{
+    int lo = 0, hi = nrep - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (first[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 // Element offset (inside the replica block) of the start of population p's
 // row at (y, z) = (0, 0).

@@ -3,18 +3,27 @@
 // normalised FFT of the whole box, averaged over shells of equal |k|).
 //
 // Per sampling step, after the step kernel has written the six fields:
-//   fft_pass_kernel<x>   packs (drho + i jx, jy + i jz, pdiag + i poff) in FP64
-//                        and transforms along x;
-//   fft_pass_kernel<y>, fft_pass_kernel<z>  transform in place along y and z;
-//   spectrum_bin_kernel  unpacks the two real fields of each array at k and -k,
-//                        forms the five spectra and sums them into shells
-//                        s = round(|n|);
+//   fft_x_kernel     packs two real fields as one complex line (drho + i pdiag,
+//                    poff + i jx, jy + i jz, and jsum = jx + jy + jz of rows
+//                    2m + i 2m + 1), transforms along x and writes the half
+//                    spectra kx = 0 .. floor(nx / 2) of the seven fields;
+//   fft_y_kernel     transforms each half spectrum in place along y;
+//   fft_zbin_kernel  transforms each half spectrum's columns along z and sums
+//                    the power of every wave vector into the shells
+//                    s = round(|n|) of that field's spectrum;
 //   spectrum_finalize_kernel  adds each shell average to the accumulators.
-// The shell sums are exact integer sums of fixed-point values, so they do not
-// depend on the order in which workgroups finish: the same state always gives
-// the same bits.  The fixed-point scale of each spectrum is 2^62 divided by
-// the sample's sum of squares of that field, which by Parseval's identity
-// bounds every partial sum of |m(k)|^2.
+// The passes run either pass by pass over all seven fields, or group by group
+// (x pass of one group, then y and z passes of its half spectra), which keeps
+// a group's half spectra in the memory-side cache between the passes.
+// Every wave vector with kx = 0 (or kx = nx / 2 for even nx) is counted once;
+// every other one stands also for its mirror -k (same shell, same power, a
+// column the half spectra do not hold) and is counted twice.  The transforms
+// run in the kernel precision, complex FP32 for the FP32 path and FP64 for the
+// FP64 path.  The shell sums are exact integer sums of fixed-point values, so
+// they do not depend on the order in which workgroups finish: the same state
+// always gives the same bits.  The fixed-point scale of each spectrum is 2^62
+// divided by the sample's sum of squares of that field, which by Parseval's
+// identity bounds every partial sum of |m(k)|^2.
 #include <hip/hip_runtime.h>
 
 #include "gmf_fft.hpp"
@@ -23,72 +32,121 @@
 namespace gmf {
 
 // ---------------------------------------------------------------------------
-// Line FFTs in LDS: mixed-radix Stockham, forward sign e^{-2 pi i / L}.
-// A stage of radix R with Ns = product of the earlier radices maps, for each
-// butterfly j < L/R with k = j mod Ns,
-//   v_r = in[j + r L/R] e^{-2 pi i k r / (Ns R)},  r < R,
-//   out[(j / Ns) Ns R + k + q Ns] = sum_r v_r e^{-2 pi i r q / R}.
+// Complex values of the transform precision Rt
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-// a * conj(t)
-__device__ __forceinline__ double2 cmulc(double2 a, double2 t)
-{
-    return make_double2(a.x * t.x + a.y * t.y, a.y * t.x - a.x * t.y);
-}
-__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
-// -i a and +i a
-__device__ __forceinline__ double2 cmi(double2 a) { return make_double2(a.y, -a.x); }
-__device__ __forceinline__ double2 cpi(double2 a) { return make_double2(-a.y, a.x); }
-
-template <int R>
-__device__ __forceinline__ void small_dft(double2 (&v)[R]);
-
+template <typename Rt>
+struct CxOf;
 template <>
-__device__ __forceinline__ void small_dft<2>(double2 (&v)[2])
+struct CxOf<float> {
+    using type = float2;
+};
+template <>
+struct CxOf<double> {
+    using type = double2;
+};
+
+__device__ __forceinline__ float2 cmake(float a, float b) { return make_float2(a, b); }
+__device__ __forceinline__ double2 cmake(double a, double b) { return make_double2(a, b); }
+
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b)
 {
-    const double2 a = v[0], b = v[1];
+    return cmake(a.x + b.x, a.y + b.y);
+}
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b)
+{
+    return cmake(a.x - b.x, a.y - b.y);
+}
+// a * conj(t)
+template <typename C>
+__device__ __forceinline__ C cmulc(C a, C t)
+{
+    return cmake(a.x * t.x + a.y * t.y, a.y * t.x - a.x * t.y);
+}
+template <typename C, typename Rt>
+__device__ __forceinline__ C cscale(C a, Rt s)
+{
+    return cmake(a.x * s, a.y * s);
+}
+// -i a and +i a
+template <typename C>
+__device__ __forceinline__ C cmi(C a)
+{
+    return cmake(a.y, -a.x);
+}
+template <typename C>
+__device__ __forceinline__ C cpi(C a)
+{
+    return cmake(-a.y, a.x);
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup barrier ordering LDS accesses only: global loads stay in flight
+// across it (a full barrier would wait for every outstanding load, the next
+// tile's too).  No thread of these kernels reads global memory that another
+// thread of its workgroup writes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// ---------------------------------------------------------------------------
+// DFTs of R points in registers, forward sign: v_q <- sum_r v_r e^{-2 pi i r q / R}.
+// ---------------------------------------------------------------------------
+template <typename Rt, typename C>
+__device__ __forceinline__ void small_dft(C (&)[1])
+{
+}
+
+template <typename Rt, typename C>
+__device__ __forceinline__ void small_dft(C (&v)[2])
+{
+    const C a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
 }
 
-template <>
-__device__ __forceinline__ void small_dft<3>(double2 (&v)[3])
+template <typename Rt, typename C>
+__device__ __forceinline__ void small_dft(C (&v)[3])
 {
     // w = e^{-2 pi i / 3} = -1/2 - i sqrt(3)/2
-    const double h = 0.86602540378443864676;   // sqrt(3) / 2
-    const double2 t1 = cadd(v[1], v[2]);
-    const double2 t2 = csub(v[0], cscale(t1, 0.5));
-    const double2 t3 = cscale(csub(v[1], v[2]), h);
+    const Rt h = (Rt)0.86602540378443864676;   // sqrt(3) / 2
+    const C t1 = cadd(v[1], v[2]);
+    const C t2 = csub(v[0], cscale(t1, (Rt)0.5));
+    const C t3 = cscale(csub(v[1], v[2]), h);
     v[0] = cadd(v[0], t1);
     v[1] = cadd(t2, cmi(t3));
     v[2] = cadd(t2, cpi(t3));
 }
 
-template <>
-__device__ __forceinline__ void small_dft<4>(double2 (&v)[4])
+template <typename Rt, typename C>
+__device__ __forceinline__ void small_dft(C (&v)[4])
 {
     // w = -i
-    const double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
-    const double2 s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
+    const C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    const C s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
     v[0] = cadd(s02, s13);
     v[2] = csub(s02, s13);
     v[1] = cadd(d02, cmi(d13));
     v[3] = cadd(d02, cpi(d13));
 }
 
-template <>
-__device__ __forceinline__ void small_dft<5>(double2 (&v)[5])
+template <typename Rt, typename C>
+__device__ __forceinline__ void small_dft(C (&v)[5])
 {
     // cos and sin of 2 pi / 5 and 4 pi / 5
-    const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
-    const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
-    const double2 b1 = cadd(v[1], v[4]), b2 = cadd(v[2], v[3]);
-    const double2 d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
-    const double2 a1 = cadd(v[0], cadd(cscale(b1, c1), cscale(b2, c2)));
-    const double2 a2 = cadd(v[0], cadd(cscale(b1, c2), cscale(b2, c1)));
-    const double2 e1 = cadd(cscale(d1, s1), cscale(d2, s2));
-    const double2 e2 = csub(cscale(d1, s2), cscale(d2, s1));
+    const Rt c1 = (Rt)0.30901699437494742410, c2 = (Rt)-0.80901699437494742410;
+    const Rt s1 = (Rt)0.95105651629515357212, s2 = (Rt)0.58778525229247312917;
+    const C b1 = cadd(v[1], v[4]), b2 = cadd(v[2], v[3]);
+    const C d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+    const C a1 = cadd(v[0], cadd(cscale(b1, c1), cscale(b2, c2)));
+    const C a2 = cadd(v[0], cadd(cscale(b1, c2), cscale(b2, c1)));
+    const C e1 = cadd(cscale(d1, s1), cscale(d2, s2));
+    const C e2 = csub(cscale(d1, s2), cscale(d2, s1));
     v[0] = cadd(v[0], cadd(b1, b2));
     v[1] = cadd(a1, cmi(e1));
     v[4] = cadd(a1, cpi(e1));
@@ -96,179 +154,581 @@ __device__ __forceinline__ void small_dft<5>(double2 (&v)[5])
     v[3] = cadd(a2, cpi(e2));
 }
 
-// One stage over W lines of length L (rows of `ld` values in buf).  twl[m] =
-// e^{+2 pi i m / L}.  Every thread reads all its butterflies before the
-// barrier and writes them after it, so the stage works in place.  P2: L is a
-// power of two (then so are L / R and Ns, and the index arithmetic is shifts
-// and masks; lnb = log2(L / R)).
-template <int R, bool P2>
-__device__ __forceinline__ void fft_stage(double2* buf, const double2* twl, uint32_t L, uint32_t W, uint32_t ld,
-                                          uint32_t Ns, uint32_t lnb)
+// cos and sin of 2 pi e / 16
+constexpr double kC1 = 0.92387953251128675613;   // cos(pi / 8)
+constexpr double kS1 = 0.38268343236508977173;   // sin(pi / 8)
+constexpr double kH = 0.70710678118654752440;    // sqrt(2) / 2
+constexpr double cos16(int e)
 {
-    constexpr uint32_t kMaxB = (kFftPoints / R + kBlock - 1) / kBlock;
-    const uint32_t nb = L / R, total = W * nb, span = L / (Ns * (uint32_t)R);
-    double2 v[kMaxB][R];
-    uint32_t dst[kMaxB];
-#pragma unroll
-    for (uint32_t q = 0; q < kMaxB; ++q) {
-        const uint32_t b = threadIdx.x + q * kBlock;
-        dst[q] = 0;
-        if (b < total) {
-            const uint32_t w = P2 ? b >> lnb : b / nb;
-            const uint32_t j = b - w * nb;
-            const uint32_t k = P2 ? j & (Ns - 1) : j % Ns;
-            const double2* line = buf + w * ld;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const double2 a = line[j + (uint32_t)r * nb];
-                v[q][r] = r == 0 ? a : cmulc(a, twl[k * (uint32_t)r * span]);
-            }
-            dst[q] = w * ld + (j - k) * (uint32_t)R + k;   // (j / Ns) Ns R + k
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (uint32_t q = 0; q < kMaxB; ++q) {
-        const uint32_t b = threadIdx.x + q * kBlock;
-        if (b < total) {
-            small_dft<R>(v[q]);
-#pragma unroll
-            for (int r = 0; r < R; ++r) buf[dst[q] + (uint32_t)r * Ns] = v[q][r];
-        }
-    }
-    __syncthreads();
+    return e == 0 ? 1.0 : e == 1 ? kC1 : e == 2 ? kH : e == 3 ? kS1 : e == 4 ? 0.0 : e == 5 ? -kS1 : e == 6 ? -kH
+         : e == 7 ? -kC1 : e == 8 ? -1.0 : e == 9 ? -kC1 : e == 10 ? -kH : e == 11 ? -kS1 : e == 12 ? 0.0
+         : e == 13 ? kS1 : e == 14 ? kH : kC1;
+}
+constexpr double sin16(int e) { return cos16((e + 12) & 15); }
+
+// a e^{-2 pi i e / 16}; e is a constant once the callers' loops are unrolled
+template <typename Rt, typename C>
+__device__ __forceinline__ C rot16(C a, int e)
+{
+    e &= 15;
+    if (e == 0) return a;
+    if (e == 4) return cmi(a);
+    if (e == 8) return cmake(-a.x, -a.y);
+    if (e == 12) return cpi(a);
+    const Rt c = (Rt)cos16(e), s = (Rt)sin16(e);
+    return cmake(a.x * c + a.y * s, a.y * c - a.x * s);
 }
 
-template <bool P2>
-__device__ __forceinline__ void fft_lines(double2* buf, const double2* twl, uint32_t L, uint32_t W, uint32_t ld)
+// R = 8 as 4 x 2: n = 2 n1 + n2, q = q1 + 4 q2
+template <typename Rt, typename C>
+__device__ __forceinline__ void small_dft(C (&v)[8])
 {
-    // the stages of fft_plan, taken from the part of L not yet transformed (no
-    // indexed array, which would live in scratch memory)
-    uint32_t Ns = 1, m = L;
-    while (m > 1) {
-        const uint32_t R = m % 4 == 0 ? 4u : (m % 2 == 0 ? 2u : (m % 3 == 0 ? 3u : 5u));
-        const uint32_t lnb = P2 ? (uint32_t)__builtin_ctz(L / R) : 0u;
-        if (P2) {
-            if (R == 4) fft_stage<4, true>(buf, twl, L, W, ld, Ns, lnb);
-            else fft_stage<2, true>(buf, twl, L, W, ld, Ns, lnb);
-        } else {
-            switch (R) {
-            case 4: fft_stage<4, false>(buf, twl, L, W, ld, Ns, 0); break;
-            case 2: fft_stage<2, false>(buf, twl, L, W, ld, Ns, 0); break;
-            case 3: fft_stage<3, false>(buf, twl, L, W, ld, Ns, 0); break;
-            default: fft_stage<5, false>(buf, twl, L, W, ld, Ns, 0); break;
+    C y[2][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 2; ++n2) {
+        C t[4] = {v[n2], v[n2 + 2], v[n2 + 4], v[n2 + 6]};
+        small_dft<Rt>(t);
+#pragma unroll
+        for (int q1 = 0; q1 < 4; ++q1) y[n2][q1] = rot16<Rt>(t[q1], 2 * n2 * q1);
+    }
+#pragma unroll
+    for (int q1 = 0; q1 < 4; ++q1) {
+        C t[2] = {y[0][q1], y[1][q1]};
+        small_dft<Rt>(t);
+        v[q1] = t[0];
+        v[q1 + 4] = t[1];
+    }
+}
+
+// R = 16 as 4 x 4: n = 4 n1 + n2, q = q1 + 4 q2
+template <typename Rt, typename C>
+__device__ __forceinline__ void small_dft(C (&v)[16])
+{
+    C y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        C t[4] = {v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]};
+        small_dft<Rt>(t);
+#pragma unroll
+        for (int q1 = 0; q1 < 4; ++q1) y[n2][q1] = rot16<Rt>(t[q1], n2 * q1);
+    }
+#pragma unroll
+    for (int q1 = 0; q1 < 4; ++q1) {
+        C t[4] = {y[0][q1], y[1][q1], y[2][q1], y[3][q1]};
+        small_dft<Rt>(t);
+#pragma unroll
+        for (int q2 = 0; q2 < 4; ++q2) v[q1 + 4 * q2] = t[q2];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Line FFTs of a tile: W lines of length L, mixed-radix Stockham.  A stage of
+// radix R with Ns = product of the earlier radices maps, for each butterfly
+// j < L/R with k = j mod Ns,
+//   v_r = in[j + r L/R] e^{-2 pi i k r / (Ns R)},  r < R,
+//   out[(j / Ns) Ns R + k + q Ns] = sum_r v_r e^{-2 pi i r q / R},
+// so the outputs come in natural order.  The first stage takes its inputs
+// from load.get(h, p) with h = load.col(w) (line w, global memory) and the
+// last one hands point p of line w to out.put(h, p, value), h = out.col(w, ok)
+// (nothing for a line with ok false); the stages between work in place on LDS
+// rows of `ld` values (point p in slot fft_phys(p)), reading every butterfly
+// of the thread before a barrier and writing after it.  WF: consecutive butterflies belong
+// to consecutive lines (the y and z passes, whose lines are the columns of a
+// half spectrum), else to one line (the x pass, whose lines are contiguous).
+// Butterflies past the tile repeat butterfly 0's loads and store nothing.
+// ---------------------------------------------------------------------------
+template <bool WF>
+__device__ __forceinline__ void butterfly(uint32_t b, const SmallDiv& dW, const SmallDiv& dnb, uint32_t& w, uint32_t& j)
+{
+    if (WF) {
+        j = dW.div(b);
+        w = b - j * dW.d;
+    } else {
+        w = dnb.div(b);
+        j = b - w * dnb.d;
+    }
+}
+
+template <int R>
+constexpr uint32_t stage_slots()
+{
+    return (kFftTilePts / R + kBlock - 1) / kBlock;
+}
+
+template <int R, bool WF, typename Rt, class Load>
+__device__ __forceinline__ void stage_first(typename CxOf<Rt>::type* buf, uint32_t L, uint32_t W, uint32_t ld,
+                                            const SmallDiv& dW, const Load& load)
+{
+    using C = typename CxOf<Rt>::type;
+    constexpr uint32_t kB = stage_slots<R>();
+    const uint32_t nb = L / R, total = W * nb;
+    const SmallDiv dnb(nb);
+    C v[kB][R];
+#pragma unroll
+    for (uint32_t q = 0; q < kB; ++q) {
+        const uint32_t b0 = threadIdx.x + q * kBlock;
+        uint32_t w, j;
+        butterfly<WF>(b0 < total ? b0 : 0u, dW, dnb, w, j);
+        const auto h = load.col(w);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = load.get(h, j + (uint32_t)r * nb);
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < kB; ++q) {
+        const uint32_t b = threadIdx.x + q * kBlock;
+        if (b < total) {
+            uint32_t w, j;
+            butterfly<WF>(b, dW, dnb, w, j);
+            small_dft<Rt>(v[q]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[w * ld + fft_phys(j * (uint32_t)R + (uint32_t)r)] = v[q][r];
+        }
+    }
+}
+
+// the inputs of a stage after the first, twiddled
+template <int R, bool WF, typename Rt>
+__device__ __forceinline__ void stage_read(const typename CxOf<Rt>::type* buf, const typename CxOf<Rt>::type* twl,
+                                           uint32_t L, uint32_t W, uint32_t ld, uint32_t Ns, const SmallDiv& dW,
+                                           const SmallDiv& dnb, const SmallDiv& dNs,
+                                           typename CxOf<Rt>::type (&v)[stage_slots<R>()][R])
+{
+    constexpr uint32_t kB = stage_slots<R>();
+    const uint32_t nb = L / R, total = W * nb, span = L / (Ns * (uint32_t)R);
+#pragma unroll
+    for (uint32_t q = 0; q < kB; ++q) {
+        const uint32_t b0 = threadIdx.x + q * kBlock;
+        uint32_t w, j;
+        butterfly<WF>(b0 < total ? b0 : 0u, dW, dnb, w, j);
+        const uint32_t k = j - dNs.div(j) * Ns;
+        const auto* line = buf + w * ld;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const auto a = line[fft_phys(j + (uint32_t)r * nb)];
+            v[q][r] = r == 0 ? a : cmulc(a, twl[k * (uint32_t)r * span]);
+        }
+    }
+}
+
+template <int R, bool WF, typename Rt>
+__device__ __forceinline__ void stage_mid(typename CxOf<Rt>::type* buf, const typename CxOf<Rt>::type* twl,
+                                          uint32_t L, uint32_t W, uint32_t ld, uint32_t Ns, const SmallDiv& dW)
+{
+    using C = typename CxOf<Rt>::type;
+    constexpr uint32_t kB = stage_slots<R>();
+    const uint32_t nb = L / R, total = W * nb;
+    const SmallDiv dnb(nb), dNs(Ns);
+    C v[kB][R];
+    stage_read<R, WF, Rt>(buf, twl, L, W, ld, Ns, dW, dnb, dNs, v);
+    lds_barrier();
+#pragma unroll
+    for (uint32_t q = 0; q < kB; ++q) {
+        const uint32_t b = threadIdx.x + q * kBlock;
+        if (b < total) {
+            uint32_t w, j;
+            butterfly<WF>(b, dW, dnb, w, j);
+            const uint32_t k = j - dNs.div(j) * Ns;
+            small_dft<Rt>(v[q]);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                buf[w * ld + fft_phys((j - k) * (uint32_t)R + k + (uint32_t)r * Ns)] = v[q][r];
+        }
+    }
+    lds_barrier();
+}
+
+// kSync: a barrier between the reads and the outputs (out writes the LDS
+// rows in place, or must follow work of other threads)
+template <int R, bool WF, bool kSync, typename Rt, class Out>
+__device__ __forceinline__ void stage_last(const typename CxOf<Rt>::type* buf, const typename CxOf<Rt>::type* twl,
+                                           uint32_t L, uint32_t W, uint32_t ld, uint32_t Ns, const SmallDiv& dW,
+                                           const Out& out)
+{
+    using C = typename CxOf<Rt>::type;
+    constexpr uint32_t kB = stage_slots<R>();
+    const uint32_t nb = L / R, total = W * nb;
+    const SmallDiv dnb(nb), dNs(Ns);
+    C v[kB][R];
+    stage_read<R, WF, Rt>(buf, twl, L, W, ld, Ns, dW, dnb, dNs, v);
+    if (kSync) lds_barrier();
+#pragma unroll
+    for (uint32_t q = 0; q < kB; ++q) {
+        const uint32_t b = threadIdx.x + q * kBlock;
+        if (b < total) {
+            uint32_t w, j;
+            butterfly<WF>(b, dW, dnb, w, j);   // here j < Ns, so k = j
+            bool ok;
+            const auto h = out.col(w, ok);
+            small_dft<Rt>(v[q]);
+            if (ok) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) out.put(h, j + (uint32_t)r * Ns, v[q][r]);
             }
+        }
+    }
+}
+
+// lines of one stage (R = L): load, transform, hand on
+template <int R, bool WF, bool kSync, typename Rt, class Load, class Out>
+__device__ __forceinline__ void stage_only(uint32_t W, const SmallDiv& dW, const Load& load, const Out& out)
+{
+    using C = typename CxOf<Rt>::type;
+    constexpr uint32_t kB = stage_slots<R>();
+    const SmallDiv d1(1u);
+    C v[kB][R];
+#pragma unroll
+    for (uint32_t q = 0; q < kB; ++q) {
+        const uint32_t b0 = threadIdx.x + q * kBlock;
+        uint32_t w, j;
+        butterfly<WF>(b0 < W ? b0 : 0u, dW, d1, w, j);
+        const auto h = load.col(w);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = load.get(h, (uint32_t)r);
+    }
+    if (kSync) lds_barrier();
+#pragma unroll
+    for (uint32_t q = 0; q < kB; ++q) {
+        const uint32_t b = threadIdx.x + q * kBlock;
+        if (b < W) {
+            uint32_t w, j;
+            butterfly<WF>(b, dW, d1, w, j);
+            bool ok;
+            const auto h = out.col(w, ok);
+            small_dft<Rt>(v[q]);
+            if (ok) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) out.put(h, (uint32_t)r, v[q][r]);
+            }
+        }
+    }
+}
+
+// Lines of 2^PL points (PL = 6 .. 10) in fixed stages p2_radix(PL, i), the
+// first of radix 16 with one butterfly per thread: p2_load takes a tile's
+// sixteen inputs per thread into registers (the loads can be issued while an
+// earlier tile is still being transformed), p2_run transforms them.
+template <bool WF, int PL, typename Rt, class Load>
+__device__ __forceinline__ void p2_load(typename CxOf<Rt>::type (&v)[16], uint32_t W, const SmallDiv& dW,
+                                        const Load& load)
+{
+    constexpr uint32_t nb = (1u << PL) / 16u;
+    const uint32_t b = threadIdx.x < W * nb ? threadIdx.x : 0u;
+    uint32_t w, j;
+    butterfly<WF>(b, dW, SmallDiv(nb), w, j);
+    const auto h = load.col(w);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = load.get(h, j + (uint32_t)r * nb);
+}
+
+template <bool WF, bool kSync, int PL, typename Rt, class Out>
+__device__ __forceinline__ void p2_run(typename CxOf<Rt>::type (&v)[16], typename CxOf<Rt>::type* buf,
+                                       const typename CxOf<Rt>::type* twl, uint32_t W, uint32_t ld,
+                                       const SmallDiv& dW, const Out& out)
+{
+    constexpr uint32_t kL = 1u << PL, nb = kL / 16u;
+    constexpr int R1 = p2_radix(PL, 1), R2 = p2_radix(PL, 2);
+    if (threadIdx.x < W * nb) {
+        uint32_t w, j;
+        butterfly<WF>(threadIdx.x, dW, SmallDiv(nb), w, j);
+        small_dft<Rt>(v);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) buf[w * ld + fft_phys(j * 16u + (uint32_t)r)] = v[r];
+    }
+    lds_barrier();
+    if constexpr (R2 == 0) {
+        stage_last<R1, WF, kSync, Rt>(buf, twl, kL, W, ld, 16u, dW, out);
+    } else {
+        stage_mid<R1, WF, Rt>(buf, twl, kL, W, ld, 16u, dW);
+        stage_last<R2, WF, kSync, Rt>(buf, twl, kL, W, ld, 16u * (uint32_t)R1, dW, out);
+    }
+}
+
+// The transform of a tile.  PL = 6 .. 10: every line has 2^PL points and the
+// stages are fixed at compile time; PL = 0: any length, the radices chosen at
+// run time (fft_next_radix).
+template <bool WF, bool kSync, int PL, typename Rt, class Load, class Out>
+__device__ __forceinline__ void fft_tile(typename CxOf<Rt>::type* buf, const typename CxOf<Rt>::type* twl, uint32_t L,
+                                         uint32_t W, uint32_t ld, const Load& load, const Out& out)
+{
+    const SmallDiv dW(W);
+    if constexpr (PL > 0) {
+        typename CxOf<Rt>::type v[16];
+        p2_load<WF, PL, Rt>(v, W, dW, load);
+        p2_run<WF, kSync, PL, Rt>(v, buf, twl, W, ld, dW, out);
+        (void)L;
+        return;
+    }
+    uint32_t R = fft_next_radix(L);
+    if (R == L) {
+        switch (R) {
+        case 16: stage_only<16, WF, kSync, Rt>(W, dW, load, out); break;
+        case 8: stage_only<8, WF, kSync, Rt>(W, dW, load, out); break;
+        case 5: stage_only<5, WF, kSync, Rt>(W, dW, load, out); break;
+        case 4: stage_only<4, WF, kSync, Rt>(W, dW, load, out); break;
+        case 3: stage_only<3, WF, kSync, Rt>(W, dW, load, out); break;
+        case 2: stage_only<2, WF, kSync, Rt>(W, dW, load, out); break;
+        default: stage_only<1, WF, kSync, Rt>(W, dW, load, out); break;
+        }
+        return;
+    }
+    switch (R) {
+    case 16: stage_first<16, WF, Rt>(buf, L, W, ld, dW, load); break;
+    case 8: stage_first<8, WF, Rt>(buf, L, W, ld, dW, load); break;
+    case 4: stage_first<4, WF, Rt>(buf, L, W, ld, dW, load); break;
+    case 2: stage_first<2, WF, Rt>(buf, L, W, ld, dW, load); break;
+    case 3: stage_first<3, WF, Rt>(buf, L, W, ld, dW, load); break;
+    default: stage_first<5, WF, Rt>(buf, L, W, ld, dW, load); break;
+    }
+    lds_barrier();
+    uint32_t Ns = R, m = L / R;
+    for (;;) {
+        R = fft_next_radix(m);
+        if (R == m) {
+            switch (R) {
+            case 16: stage_last<16, WF, kSync, Rt>(buf, twl, L, W, ld, Ns, dW, out); break;
+            case 8: stage_last<8, WF, kSync, Rt>(buf, twl, L, W, ld, Ns, dW, out); break;
+            case 4: stage_last<4, WF, kSync, Rt>(buf, twl, L, W, ld, Ns, dW, out); break;
+            case 2: stage_last<2, WF, kSync, Rt>(buf, twl, L, W, ld, Ns, dW, out); break;
+            case 3: stage_last<3, WF, kSync, Rt>(buf, twl, L, W, ld, Ns, dW, out); break;
+            default: stage_last<5, WF, kSync, Rt>(buf, twl, L, W, ld, Ns, dW, out); break;
+            }
+            return;
+        }
+        switch (R) {
+        case 16: stage_mid<16, WF, Rt>(buf, twl, L, W, ld, Ns, dW); break;
+        case 8: stage_mid<8, WF, Rt>(buf, twl, L, W, ld, Ns, dW); break;
+        case 4: stage_mid<4, WF, Rt>(buf, twl, L, W, ld, Ns, dW); break;
+        case 2: stage_mid<2, WF, Rt>(buf, twl, L, W, ld, Ns, dW); break;
+        case 3: stage_mid<3, WF, Rt>(buf, twl, L, W, ld, Ns, dW); break;
+        default: stage_mid<5, WF, Rt>(buf, twl, L, W, ld, Ns, dW); break;
         }
         Ns *= R;
         m /= R;
     }
 }
 
-// Replica of workgroup b: first[r] <= b < first[r + 1] (first[0] = 0).
-__device__ __forceinline__ int replica_of_block(const uint32_t* first, int32_t nrep, uint32_t b)
+// twl[m] = e^{+2 pi i m / L} in the transform precision, from the FP64 table
+template <typename Rt>
+__device__ __forceinline__ void load_twiddles(typename CxOf<Rt>::type* twl, const double2* __restrict__ tw, uint32_t L)
 {
-    int lo = 0, hi = nrep - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        if (first[mid] <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
+    for (uint32_t m = threadIdx.x; m < L; m += kBlock) twl[m] = cmake((Rt)tw[m].x, (Rt)tw[m].y);
 }
 
-// One pass of the 3D transform along AXIS for packed array `arr`, tile `tile`
-// of replica R.  AXIS 0 builds the packed values from the sampled fields.
-// P2: the line length L and the lines per tile W are powers of two (the
-// index arithmetic is then shifts and masks).
-template <typename T, int AXIS, bool P2>
-__device__ __forceinline__ void fft_pass_body(const RepDev& R, uint32_t tile, uint32_t arr, uint32_t L, uint32_t W,
-                                              const T* __restrict__ fields, const double2* __restrict__ tw,
-                                              double2* spec, double2* lds)
-{
-    const uint32_t nx = R.nx, ny = R.ny, nz = R.nz;
-    const uint32_t ld = L + 1;
-    const uint32_t lL = P2 ? (uint32_t)__builtin_ctz(L) : 0u, lW = P2 ? (uint32_t)__builtin_ctz(W) : 0u;
-    double2* buf = lds;
-    double2* twl = lds + W * ld;
-    const uint32_t toff = R.tw_offset + (AXIS == 0 ? 0u : (AXIS == 1 ? nx : nx + ny));
-    for (uint32_t m = threadIdx.x; m < L; m += kBlock) twl[m] = tw[toff + m];
-
-    // tile origin: AXIS 0: rows tile*W ..; AXIS 1/2: columns x0 .. x0+W-1 of plane z (AXIS 1) or row y (AXIS 2)
-    uint32_t row0 = 0, x0 = 0, fixed = 0;
-    if (AXIS == 0) {
-        row0 = tile * W;
-    } else {
-        const uint32_t per = (nx + W - 1) / W;
-        fixed = tile / per;
-        x0 = (tile - fixed * per) * W;
-    }
-    const uint64_t N = R.n;
-    double2* S = spec + R.spec_offset + (uint64_t)arr * N;
-    const uint32_t tot = W * L;
-    auto node_of = [&](uint32_t i, uint32_t& w, uint32_t& j, uint32_t& node) -> bool {
-        if (AXIS == 0) {
-            w = P2 ? i >> lL : i / L;
-            j = i - w * L;
-            const uint32_t row = row0 + w;
-            node = row * nx + j;
-            return row < ny * nz;
-        }
-        j = P2 ? i >> lW : i / W;
-        w = i - j * W;
-        const uint32_t x = x0 + w;
-        node = AXIS == 1 ? x + nx * (j + ny * fixed) : x + nx * (fixed + ny * j);
-        return x < nx;
+// ---------------------------------------------------------------------------
+// Line sources and sinks of the passes (see fft_tile).
+// ---------------------------------------------------------------------------
+// x pass: the tile's 3 RT lines are RT rows in three kinds (kind-major, line
+// w = kind RT + row), each two real rows packed as a + i b: kind 0
+// drho + i pdiag, 1 poff + i jx, 2 jy + i jz.  A row past the box reads row 0
+// and is never stored.
+template <typename T, typename Rt>
+struct XSrc {
+    using C = typename CxOf<Rt>::type;
+    const T* F;   // the six fields, N values apart
+    uint64_t N;
+    uint32_t nx, row0, RT, rows;
+    SmallDiv dRT;
+    struct H {
+        const T* a;
+        const T* b;
     };
-    // all global loads of the thread are issued before the first LDS store
-    constexpr uint32_t kPer = kFftPoints / kBlock;
-    double2 v[kPer];
-    uint32_t at[kPer];
-#pragma unroll
-    for (uint32_t q = 0; q < kPer; ++q) {
-        const uint32_t i = threadIdx.x + q * kBlock;
-        uint32_t w = 0, j = 0, node = 0;
-        v[q] = make_double2(0.0, 0.0);
-        at[q] = ~0u;
-        if (i < tot) {
-            if (node_of(i, w, j, node)) {
-                if (AXIS == 0) {
-                    const T* F = fields + R.field_offset + (uint64_t)(2 * arr) * N;
-                    v[q] = make_double2((double)F[node], (double)F[N + node]);
-                } else {
-                    v[q] = S[node];
-                }
-            }
-            at[q] = w * ld + j;
-        }
+    __device__ __forceinline__ H col(uint32_t w) const
+    {
+        const uint32_t kind = dRT.div(w), r = row0 + (w - kind * RT);
+        const uint64_t base = (uint64_t)(r < rows ? r : 0u) * nx;
+        // fields of each kind: (0, 4), (5, 1), (2, 3)
+        const uint32_t fa = kind == 0 ? 0u : (kind == 1 ? 5u : 2u), fb = kind == 0 ? 4u : (kind == 1 ? 1u : 3u);
+        return H{F + fa * N + base, F + fb * N + base};
     }
+    __device__ __forceinline__ C get(const H& h, uint32_t p) const { return cmake((Rt)h.a[p], (Rt)h.b[p]); }
+};
+
+// rows of ld values in LDS, point p in slot fft_phys(p)
+template <typename C>
+struct LdsRows {
+    C* buf;
+    uint32_t ld;
+    __device__ __forceinline__ C* col(uint32_t w, bool& ok) const
+    {
+        ok = true;
+        return buf + w * ld;
+    }
+    __device__ __forceinline__ void put(C* h, uint32_t p, C v) const { h[fft_phys(p)] = v; }
+};
+
+// the columns of a tile as lines of points lstride values apart
+template <typename C>
+struct ColLines {
+    C* S;
+    ColTile t;
+    SmallDiv dcw;
+    uint32_t pstride, lstride;
+    __device__ __forceinline__ C* col(uint32_t w, bool& ok) const
+    {
+        uint32_t off, plane, kx;
+        ok = col_offset(t, dcw, pstride, w, off, plane, kx);
+        return S + off;
+    }
+    __device__ __forceinline__ const C* col(uint32_t w) const
+    {
+        bool ok;
+        return col(w, ok);
+    }
+    __device__ __forceinline__ C get(const C* h, uint32_t p) const { return h[p * lstride]; }
+    __device__ __forceinline__ void put(C* h, uint32_t p, C v) const { h[p * lstride] = v; }
+};
+
+// ---------------------------------------------------------------------------
+// The tiles of workgroup wg: one (the generic kernels), or up to
+// kFftTilesPerWG (the kernels with fixed stages), whose first-stage inputs
+// are loaded while the previous tile is transformed.  run(tile, v) transforms
+// a tile from its inputs v and uses the result; the LDS rows are free again
+// after it.
+// ---------------------------------------------------------------------------
+template <uint32_t TPW, bool WF, int PL, typename Rt, class Make, class Run>
+__device__ __forceinline__ void pipelined_tiles(uint32_t wg, uint32_t ntiles, uint32_t W, const SmallDiv& dW,
+                                                const Make& make, const Run& run)
+{
+    using C = typename CxOf<Rt>::type;
+    // tiles wg, wg + G, wg + 2 G, ... (G workgroups): the workgroups resident at
+    // one time work on neighbouring tiles, which share DRAM pages
+    const uint32_t G = (ntiles + TPW - 1) / TPW;
+    auto tile_of = [&](uint32_t k) { return wg + k * G < ntiles ? wg + k * G : wg; };
+    // two register buffers in turn (a copy between them would wait for the loads)
+    C va[16], vb[16];
+    p2_load<WF, PL, Rt>(va, W, dW, make(tile_of(0)));
 #pragma unroll
-    for (uint32_t q = 0; q < kPer; ++q)
-        if (at[q] != ~0u) buf[at[q]] = v[q];
-    __syncthreads();
-    fft_lines<P2>(buf, twl, L, W, ld);
-#pragma unroll
-    for (uint32_t q = 0; q < kPer; ++q) {
-        const uint32_t i = threadIdx.x + q * kBlock;
-        uint32_t w, j, node;
-        if (i < tot && node_of(i, w, j, node)) S[node] = buf[w * ld + j];
+    for (uint32_t k = 0; k < TPW; ++k) {
+        const bool live = wg + k * G < ntiles;
+        if (k % 2 == 0) {
+            if (k + 1 < TPW) p2_load<WF, PL, Rt>(vb, W, dW, make(tile_of(k + 1)));
+            if (live) run(tile_of(k), va);
+        } else {
+            if (k + 1 < TPW) p2_load<WF, PL, Rt>(va, W, dW, make(tile_of(k + 1)));
+            if (live) run(tile_of(k), vb);
+        }
+        if (k + 1 < TPW) lds_barrier();
     }
 }
 
-template <typename T, int AXIS>
-__global__ __launch_bounds__(kBlock) void fft_pass_kernel(const RepDev* reps, const uint32_t* first, int32_t nrep,
-                                                          const T* __restrict__ fields,
-                                                          const double2* __restrict__ tw, double2* spec)
+// ---------------------------------------------------------------------------
+// x pass: RT rows of the box per tile, each as three complex lines (XSrc)
+// transformed along x; the half spectra of a and b of a line follow from
+// A(k) = (Z(k) + conj Z(-k)) / 2 and B(k) = (Z(k) - conj Z(-k)) / (2 i), with
+// Z(-k) in the same LDS row, and that of jsum = jx + jy + jz from theirs.
+// ---------------------------------------------------------------------------
+template <typename T, typename Rt, int PL>
+__device__ __forceinline__ void fft_x_body(const RepDev& R, uint32_t wg, const T* __restrict__ fields,
+                                           const double2* __restrict__ tw, typename CxOf<Rt>::type* spec,
+                                           typename CxOf<Rt>::type* lds)
 {
-    extern __shared__ double2 lds[];
+    using C = typename CxOf<Rt>::type;
+    const uint32_t nx = R.nx, ny = R.ny, nz = R.nz, L = nx;
+    const uint32_t RT = fft_x_rows(nx), NL = kFftXKinds * RT, ld = fft_ld(0, nx, ny, nz, sizeof(C));
+    const uint32_t H = half_len(nx), Hp = half_stride(nx), rows = ny * nz;
+    C* buf = lds;
+    C* twl = lds + NL * ld;
+    load_twiddles<Rt>(twl, tw + R.tw_offset, L);
+    const T* F = fields + R.field_offset;
+    const uint64_t N = R.n;
+    const SmallDiv dH(H), dRT(RT), dW(NL);
+    auto make = [&](uint32_t tile) { return XSrc<T, Rt>{F, N, nx, tile * RT, RT, rows, dRT}; };
+    const LdsRows<C> out{buf, ld};
+    C* S = spec + R.spec_offset;
+    const uint64_t HN = (uint64_t)Hp * rows;
+    // the seven half spectra of the tile's rows from its transformed lines in LDS
+    auto separate = [&](uint32_t tile) {
+        const uint32_t row0 = tile * RT;
+        for (uint32_t i = threadIdx.x; i < RT * H; i += kBlock) {
+            const uint32_t w = dH.div(i), kx = i - w * H, row = row0 + w;
+            if (row >= rows) continue;
+            const uint32_t km = kx == 0 ? 0u : L - kx;
+            const uint64_t o = (uint64_t)row * Hp + kx;
+            C js = cmake((Rt)0, (Rt)0);
+#pragma unroll
+            for (uint32_t kind = 0; kind < kFftXKinds; ++kind) {
+                const C* line = buf + (kind * RT + w) * ld;
+                const C Z = line[fft_phys(kx)], Zm = line[fft_phys(km)];
+                const C A = cmake((Rt)0.5 * (Z.x + Zm.x), (Rt)0.5 * (Z.y - Zm.y));
+                const C B = cmake((Rt)0.5 * (Z.y + Zm.y), (Rt)-0.5 * (Z.x - Zm.x));
+                const uint32_t fa = kind == 0 ? 0u : (kind == 1 ? 5u : 2u), fb = kind == 0 ? 4u : (kind == 1 ? 1u : 3u);
+                S[(uint64_t)fa * HN + o] = A;
+                S[(uint64_t)fb * HN + o] = B;
+                // jx is kind 1's second field, jy and jz kind 2's
+                if (kind == 1) js = B;
+                if (kind == 2) js = cadd(js, cadd(A, B));
+            }
+            S[(uint64_t)6 * HN + o] = js;
+        }
+    };
+    if constexpr (PL > 0) {
+        auto run = [&](uint32_t tile, C (&v)[16]) {
+            p2_run<false, true, PL, Rt>(v, buf, twl, NL, ld, dW, out);
+            lds_barrier();
+            separate(tile);
+        };
+        pipelined_tiles<kFftTilesPerWG[0], false, PL, Rt>(wg, fft_x_tiles(nx, ny, nz), NL, dW, make, run);
+    } else {
+        fft_tile<false, true, 0, Rt>(buf, twl, L, NL, ld, make(wg), out);
+        lds_barrier();
+        separate(wg);
+    }
+}
+
+template <typename T, typename Rt, int PL>
+__global__ __launch_bounds__(kBlock) void fft_x_kernel(const RepDev* reps, const uint32_t* first, int32_t nrep,
+                                                       const T* __restrict__ fields, const double2* __restrict__ tw,
+                                                       typename CxOf<Rt>::type* spec)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    using C = typename CxOf<Rt>::type;
     const int r = replica_of_block(first, nrep, blockIdx.x);
     const RepDev& R = reps[r];
-    const uint32_t tile = blockIdx.x - first[r];
-    const uint32_t L = fft_axis_len(AXIS, R.nx, R.ny, R.nz);
-    const uint32_t W = fft_tile_lines(AXIS, L, R.nx);
-    if ((L & (L - 1)) == 0 && (W & (W - 1)) == 0)
-        fft_pass_body<T, AXIS, true>(R, tile, blockIdx.y, L, W, fields, tw, spec, lds);
-    else
-        fft_pass_body<T, AXIS, false>(R, tile, blockIdx.y, L, W, fields, tw, spec, lds);
+    if (fft_class(R.nx) != PL) return;
+    fft_x_body<T, Rt, PL>(R, blockIdx.x - first[r], fields, tw, spec, reinterpret_cast<C*>(lds_raw));
+}
+
+// ---------------------------------------------------------------------------
+// y pass: tiles of columns of half spectrum `fld`, transformed along y in place.
+// ---------------------------------------------------------------------------
+template <typename Rt, int PL>
+__device__ __forceinline__ void fft_y_body(const RepDev& R, uint32_t wg, uint32_t fld, const double2* __restrict__ tw,
+                                           typename CxOf<Rt>::type* spec, typename CxOf<Rt>::type* lds)
+{
+    using C = typename CxOf<Rt>::type;
+    const uint32_t nx = R.nx, ny = R.ny, nz = R.nz, L = ny;
+    const FftCols cols = fft_cols(1, nx, ny, nz);
+    const uint32_t W = cols.W, ld = fft_ld(1, nx, ny, nz, sizeof(C)), Hp = half_stride(nx);
+    C* buf = lds;
+    C* twl = lds + W * ld;
+    load_twiddles<Rt>(twl, tw + R.tw_offset + nx, L);
+    C* Sf = spec + R.spec_offset + (uint64_t)fld * Hp * ny * nz;
+    auto make = [&](uint32_t tile) {
+        const ColTile t = col_tile(cols, tile);
+        return ColLines<C>{Sf, t, SmallDiv(t.cw), ny * Hp, Hp};
+    };
+    const SmallDiv dW(W);
+    if constexpr (PL > 0) {
+        auto run = [&](uint32_t tile, C (&v)[16]) { p2_run<true, false, PL, Rt>(v, buf, twl, W, ld, dW, make(tile)); };
+        pipelined_tiles<kFftTilesPerWG[1], true, PL, Rt>(wg, cols.tiles(), W, dW, make, run);
+    } else {
+        const auto io = make(wg);
+        fft_tile<true, false, 0, Rt>(buf, twl, L, W, ld, io, io);
+    }
+}
+
+// grid.y runs over the fields of flist (four bits per field)
+template <typename Rt, int PL>
+__global__ __launch_bounds__(kBlock) void fft_y_kernel(const RepDev* reps, const uint32_t* first, int32_t nrep,
+                                                       uint32_t flist, const double2* __restrict__ tw,
+                                                       typename CxOf<Rt>::type* spec)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    using C = typename CxOf<Rt>::type;
+    const int r = replica_of_block(first, nrep, blockIdx.x);
+    if (fft_class(reps[r].ny) != PL) return;
+    fft_y_body<Rt, PL>(reps[r], blockIdx.x - first[r], (flist >> (4u * blockIdx.y)) & 15u, tw, spec,
+                       reinterpret_cast<C*>(lds_raw));
 }
 
 // Fixed-point scale of each spectrum for the current sample: 2^62 / bound,
@@ -281,154 +741,234 @@ __device__ __forceinline__ void spectrum_scales(const double* ssq, double (&scal
     for (int m = 0; m < kSpec; ++m) scale[m] = bound[m] > 0.0 ? 0x1p62 / bound[m] : 0.0;
 }
 
-// Each wavefront takes kBinPoints / 4 consecutive wave vectors of the half
-// space that bin_nodes() describes, 64 at a time (one per lane, so the loads
-// of k and of -k are contiguous).  The spectra of real fields take equal
-// values at k and -k, so a wave vector whose partner -k lies outside that
-// range counts twice, one that is its own partner once, and the upper member
-// of a pair inside the range not at all: every wave vector of the box is
-// counted once, with half the loads.  Neighbouring
-// lanes mostly share a shell: a segmented scan over the lanes, keyed by the
-// shell, sums the five powers of each run of equal shell in FP64, and the last
-// lane of each run adds its rounded fixed-point value to the workgroup's shell
-// bins in LDS.
-__global__ __launch_bounds__(kBlock) void spectrum_bin_kernel(const RepDev* reps, const uint32_t* first, int32_t nrep,
-                                                              const double2* __restrict__ spec,
-                                                              const double* __restrict__ sample_sq,
-                                                              unsigned long long* bins)
-{
-    extern __shared__ unsigned long long lbin[];
-    const int r = replica_of_block(first, nrep, blockIdx.x);
-    const RepDev& R = reps[r];
-    const uint32_t ns = R.nshell;
-    for (uint32_t i = threadIdx.x; i < ns * kSpec; i += kBlock) lbin[i] = 0ull;
-    double scale[kSpec];
-    spectrum_scales(sample_sq + (size_t)r * kObs, scale);
-    __syncthreads();
+// Spectrum of half spectrum f (drho, jx, jy, jz, pdiag, poff, jsum): rho, j
+// (the mean over three fields), jsum, pdiag, poff.
+__device__ __forceinline__ int spectrum_of_field(uint32_t f) { return f == 0 ? 0 : (f <= 3 ? 1 : (f == 6 ? 2 : (int)f - 1)); }
 
-    const uint32_t nx = R.nx, ny = R.ny, nz = R.nz;
-    const uint64_t N = R.n;
-    const double invn = 1.0 / (double)N;
-    const double2* Z = spec + R.spec_offset;
-    const int lane = (int)(threadIdx.x & 63u);
-    const uint32_t wave = threadIdx.x >> 6;
-    const uint64_t Nh = bin_nodes(nx, ny, nz);
-    const uint32_t base = (blockIdx.x - first[r]) * kBinPoints + wave * (kBinPoints / (kBlock / 64));
-    for (uint32_t it = 0; it < kBinPoints / kBlock; ++it) {
-        const uint32_t n = base + it * 64u + (uint32_t)lane;
-        double v[kSpec] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        uint32_t s = 0;   // 0: no contribution (k = 0, past the half space, or counted at -k)
-        if (n < Nh) {
-            const uint32_t yz = fdiv(n, R.divx);
-            const uint32_t x = n - yz * nx;
-            const uint32_t z = fdiv(yz, R.divy);
-            const uint32_t y = yz - z * ny;
-            // -k
-            const uint32_t mx = x == 0 ? 0 : nx - x, my = y == 0 ? 0 : ny - y, mz = z == 0 ? 0 : nz - z;
-            const uint32_t mn = mx + nx * (my + ny * mz);
-            const int64_t fx = signed_freq(x, nx), fy = signed_freq(y, ny), fz = signed_freq(z, nz);
-            const uint64_t n2 = (uint64_t)(fx * fx + fy * fy + fz * fz);
-            if (n2 > 0 && (mn >= Nh || n <= mn)) {
-                s = shell_of(n2);
-                const double wk = n == mn ? invn : 2.0 * invn;   // 1/N per wave vector counted
-                double2 X[2 * kFftArrays];
-#pragma unroll
-                for (int c = 0; c < kFftArrays; ++c) {
-                    const double2 A = Z[(uint64_t)c * N + n], B = Z[(uint64_t)c * N + mn];
-                    // A = F(k) + i G(k), B = F(-k) + i G(-k) for transforms F, G of real fields:
-                    // F(k) = (A + conj B) / 2, G(k) = (A - conj B) / (2 i)
-                    X[2 * c] = make_double2(0.5 * (A.x + B.x), 0.5 * (A.y - B.y));
-                    X[2 * c + 1] = make_double2(0.5 * (A.y + B.y), -0.5 * (A.x - B.x));
-                }
-                // X: drho, jx, jy, jz, pdiag, poff
-                const double2 js = make_double2(X[1].x + X[2].x + X[3].x, X[1].y + X[2].y + X[3].y);
-                auto pw = [](double2 a) { return a.x * a.x + a.y * a.y; };
-                v[0] = pw(X[0]) * wk;
-                v[1] = (pw(X[1]) + pw(X[2]) + pw(X[3])) * (wk / 3.0);
-                v[2] = pw(js) * wk;
-                v[3] = pw(X[4]) * wk;
-                v[4] = pw(X[5]) * wk;
-            }
-        }
-        // segmented inclusive scan over the lanes; a run starts where the shell changes
-        const uint32_t s_prev = (uint32_t)__shfl_up((int)s, 1, 64);
-        const uint32_t s_next = (uint32_t)__shfl_down((int)s, 1, 64);
-        int flag = (lane == 0 || s_prev != s) ? 1 : 0;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            double pv[kSpec];
-#pragma unroll
-            for (int m = 0; m < kSpec; ++m) pv[m] = __shfl_up(v[m], d, 64);
-            const int pf = __shfl_up(flag, d, 64);
-            if (lane >= d && !flag) {
-#pragma unroll
-                for (int m = 0; m < kSpec; ++m) v[m] += pv[m];
-                flag = pf;
-            }
-        }
-        const bool tail = lane == 63 || s_next != s;
-        if (tail && s > 0) {
-#pragma unroll
-            for (int m = 0; m < kSpec; ++m) {
-                const unsigned long long q = (unsigned long long)(v[m] * scale[m] + 0.5);
-                if (q) atomicAdd(&lbin[s * kSpec + m], q);
-            }
-        }
-    }
-    __syncthreads();
-    unsigned long long* gb = bins + (size_t)R.shell_offset * kSpec;
-    for (uint32_t i = threadIdx.x; i < ns * kSpec; i += kBlock)
-        if (lbin[i]) atomicAdd(&gb[i], lbin[i]);
+// floor(|x|^2 sc + 1/2) for 0 <= |x|^2 sc < 2^63: the power in the transform
+// precision, scaled in FP64, converted as two exact 32-bit halves
+__device__ __forceinline__ double power_of(float2 x) { return (double)fmaf(x.x, x.x, x.y * x.y); }
+__device__ __forceinline__ double power_of(double2 x) { return fma(x.x, x.x, x.y * x.y); }
+template <typename C>
+__device__ __forceinline__ unsigned long long fixed_power(C x, double sc)
+{
+    const double q = fma(power_of(x), sc, 0.5);
+    const uint32_t hi = (uint32_t)(q * 0x1p-32);
+    const uint32_t lo = (uint32_t)fma((double)hi, -0x1p32, q);
+    return ((unsigned long long)hi << 32) | lo;
 }
 
-// Shell averages of the sample into the FP64 accumulators; the integer bins
-// are cleared for the next sample.
+// ---------------------------------------------------------------------------
+// z pass and shell sums: tiles of columns of half spectrum `fld`, transformed
+// along z into LDS; then each column's wave vectors in runs of |fz| (fz and
+// -fz together): the power of each in FP64 times its weight (1/N, twice for a
+// wave vector that stands also for its mirror -k), rounded to the spectrum's
+// fixed point and summed while the shell stays the same (it grows with |fz|,
+// by at most one per step), each run's sum added to the workgroup's shell
+// bins in LDS by one integer atomic (exact, so the order does not matter);
+// after the workgroup's tiles the bins go to copy `copy` of the replica's bins.
+// ---------------------------------------------------------------------------
+template <typename Rt, int PL>
+__device__ __forceinline__ void fft_zbin_body(const RepDev& R, uint32_t wg, uint32_t fld,
+                                              const double2* __restrict__ tw,
+                                              const typename CxOf<Rt>::type* __restrict__ spec,
+                                              const double* __restrict__ ssq, unsigned long long* bins,
+                                              uint32_t copy, uint32_t bin_stride, unsigned char* lds_raw)
+{
+    using C = typename CxOf<Rt>::type;
+    const uint32_t nx = R.nx, ny = R.ny, nz = R.nz, L = nz;
+    const FftCols cols = fft_cols(2, nx, ny, nz);
+    const uint32_t W = cols.W, ld = fft_ld(2, nx, ny, nz, sizeof(C)), Hp = half_stride(nx);
+    C* buf = reinterpret_cast<C*>(lds_raw);
+    C* twl = buf + W * ld;
+    const uint32_t bin_off = ((uint32_t)sizeof(C) * (W * ld + L) + 7u) / 8u * 8u;
+    unsigned long long* lbin = reinterpret_cast<unsigned long long*>(lds_raw + bin_off);
+    const uint32_t ns = R.nshell;
+    for (uint32_t i = threadIdx.x; i < ns; i += kBlock) lbin[i] = 0ull;
+    load_twiddles<Rt>(twl, tw + R.tw_offset + nx + ny, L);
+    C* Sf = const_cast<C*>(spec) + R.spec_offset + (uint64_t)fld * Hp * ny * nz;
+    auto make = [&](uint32_t tile) {
+        const ColTile t = col_tile(cols, tile);
+        return ColLines<C>{Sf, t, SmallDiv(t.cw), Hp, ny * Hp};
+    };
+    const LdsRows<C> out{buf, ld};
+
+    double scale[kSpec];
+    spectrum_scales(ssq, scale);
+    const int m = spectrum_of_field(fld);
+    const double sc1 = scale[m] * (fld >= 1 && fld <= 3 ? 1.0 / 3.0 : 1.0) / (double)R.n, sc2 = 2.0 * sc1;
+    // items: (column w, run c of CH values a = |fz|, a = 0 .. L/2)
+    const uint32_t na = L / 2 + 1;
+    const uint32_t CH = (na * W + kBlock - 1) / kBlock, nch = (na + CH - 1) / CH;
+    const SmallDiv dW(W);
+    auto bin = [&](uint32_t tile) {
+        const ColTile t = col_tile(cols, tile);
+        const SmallDiv dcw(t.cw);
+        for (uint32_t i = threadIdx.x; i < nch * W; i += kBlock) {
+            const uint32_t c = dW.div(i), w = i - c * W;
+            uint32_t off, plane, kx;
+            if (!col_offset(t, dcw, Hp, w, off, plane, kx)) continue;
+            const C* line = buf + w * ld;
+            const int32_t fy = signed_freq(plane, ny);
+            const uint32_t c0 = kx * kx + (uint32_t)(fy * fy);
+            const double sc = (kx == 0u || 2u * kx == nx) ? sc1 : sc2;
+            const uint32_t a0 = c * CH, a1 = a0 + CH < na ? a0 + CH : na;
+            const uint32_t n20 = c0 + a0 * a0;
+            uint32_t s = shell_from_root(n20, __builtin_amdgcn_sqrtf((float)n20));
+            unsigned long long acc = 0ull;
+            for (uint32_t a = a0; a < a1; ++a) {
+                const uint32_t n2 = c0 + a * a;
+                if (n2 == 0u) continue;   // k = 0
+                if ((2u * s + 1u) * (2u * s + 1u) <= 4u * n2) {
+                    if (acc) atomicAdd(&lbin[s], acc);
+                    acc = 0ull;
+                    ++s;
+                }
+                acc += fixed_power(line[fft_phys(a)], sc);
+                const uint32_t zm = L - a;   // fz = -a
+                if (a != 0u && zm != a) acc += fixed_power(line[fft_phys(zm)], sc);
+            }
+            if (acc) atomicAdd(&lbin[s], acc);
+        }
+    };
+    if constexpr (PL > 0) {
+        auto run = [&](uint32_t tile, C (&v)[16]) {
+            p2_run<true, true, PL, Rt>(v, buf, twl, W, ld, dW, out);
+            lds_barrier();
+            bin(tile);
+        };
+        pipelined_tiles<kFftTilesPerWG[2], true, PL, Rt>(wg, cols.tiles(), W, dW, make, run);
+    } else {
+        fft_tile<true, true, 0, Rt>(buf, twl, L, W, ld, make(wg), out);
+        lds_barrier();
+        bin(wg);
+    }
+    lds_barrier();
+    unsigned long long* gb = bins + (size_t)copy * bin_stride + (size_t)R.shell_offset * kSpec;
+    for (uint32_t i = threadIdx.x; i < ns; i += kBlock)
+        if (lbin[i]) atomicAdd(&gb[(size_t)i * kSpec + m], lbin[i]);
+}
+
+template <typename Rt, int PL>
+__global__ __launch_bounds__(kBlock) void fft_zbin_kernel(const RepDev* reps, const uint32_t* first, int32_t nrep,
+                                                          uint32_t flist, const double2* __restrict__ tw,
+                                                          const typename CxOf<Rt>::type* __restrict__ spec,
+                                                          const double* __restrict__ sample_sq,
+                                                          unsigned long long* bins, uint32_t bin_stride)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int r = replica_of_block(first, nrep, blockIdx.x);
+    if (fft_class(reps[r].nz) != PL) return;
+    fft_zbin_body<Rt, PL>(reps[r], blockIdx.x - first[r], (flist >> (4u * blockIdx.y)) & 15u, tw, spec,
+                          sample_sq + (size_t)r * kObs, bins, (blockIdx.x + blockIdx.y) % kBinCopies, bin_stride,
+                          lds_raw);
+}
+
+// Shell averages of the sample into the FP64 accumulators: each bin is the
+// sum of its kBinCopies copies (bin_stride values apart), one thread per bin
+// (grid.y: replica); the copies are cleared for the next sample.
 __global__ __launch_bounds__(kBlock) void spectrum_finalize_kernel(const RepDev* reps, const double* sample_sq,
                                                                    const int64_t* counts,
-                                                                   unsigned long long* bins, double* sacc)
+                                                                   unsigned long long* bins, uint32_t bin_stride,
+                                                                   double* sacc)
 {
-    const RepDev& R = reps[blockIdx.x];
+    const RepDev& R = reps[blockIdx.y];
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= R.nshell * kSpec) return;
     double scale[kSpec];
-    spectrum_scales(sample_sq + (size_t)blockIdx.x * kObs, scale);
-    const uint32_t base = R.shell_offset;
-    for (uint32_t i = threadIdx.x; i < R.nshell * kSpec; i += kBlock) {
-        const uint32_t s = i / kSpec, m = i - s * kSpec;
-        const unsigned long long q = bins[(size_t)base * kSpec + i];
-        const int64_t c = counts[base + s];
-        if (c > 0 && scale[m] > 0.0) sacc[(size_t)base * kSpec + i] += ((double)q / scale[m]) / (double)c;
-        bins[(size_t)base * kSpec + i] = 0ull;
+    spectrum_scales(sample_sq + (size_t)blockIdx.y * kObs, scale);
+    const uint32_t s = i / kSpec, m = i - s * kSpec;
+    unsigned long long* b = bins + (size_t)R.shell_offset * kSpec + i;
+    unsigned long long v[kBinCopies];
+#pragma unroll
+    for (uint32_t k = 0; k < kBinCopies; ++k) v[k] = b[(size_t)k * bin_stride];
+    unsigned long long q = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kBinCopies; ++k) {
+        q += v[k];
+        b[(size_t)k * bin_stride] = 0ull;
     }
+    const int64_t c = counts[R.shell_offset + s];
+    if (c > 0 && scale[m] > 0.0) sacc[(size_t)R.shell_offset * kSpec + i] += ((double)q / scale[m]) / (double)c;
+}
+
+// y- and z-pass field groups of order 1 (four bits per field)
+constexpr int kFieldGroups = 4;
+constexpr uint32_t kGroupFields[kFieldGroups] = {0x40u, 0x15u, 0x32u, 0x6u};
+constexpr uint32_t kGroupFieldCount[kFieldGroups] = {2u, 2u, 2u, 1u};
+
+// One pass's kernel for the plan PL of its lines (see fft_tile).
+template <typename T, typename Rt, int PL>
+static void launch_pass(int axis, dim3 grid, size_t lds, hipStream_t s, const RepDev* reps, const uint32_t* first,
+                        int32_t nrep, uint32_t list, const T* fields, const double2* tw,
+                        typename CxOf<Rt>::type* sp, const double* sample_sq, unsigned long long* bins,
+                        uint32_t bin_stride)
+{
+    if (axis == 0)
+        fft_x_kernel<T, Rt, PL><<<grid, kBlock, lds, s>>>(reps, first, nrep, fields, tw, sp);
+    else if (axis == 1)
+        fft_y_kernel<Rt, PL><<<grid, kBlock, lds, s>>>(reps, first, nrep, list, tw, sp);
+    else
+        fft_zbin_kernel<Rt, PL><<<grid, kBlock, lds, s>>>(reps, first, nrep, list, tw, sp, sample_sq, bins, bin_stride);
+}
+
+template <typename T, typename Rt>
+static hipError_t launch_spectrum_t(const RepDev* reps, int32_t nrep, const uint32_t* first, const uint32_t* nblk,
+                                    const T* fields, const double2* tw, void* spec, const double* sample_sq,
+                                    const int64_t* counts, unsigned long long* bins, uint32_t bin_stride, double* sacc,
+                                    uint32_t max_nshell, const size_t* lds, const uint32_t* classes, int order,
+                                    hipStream_t s)
+{
+    using C = typename CxOf<Rt>::type;
+    C* sp = static_cast<C*>(spec);
+    const size_t stride = (size_t)nrep + 1;
+    // one launch per kernel class present along the axis (bit c of classes[axis])
+    auto pass = [&](int axis, uint32_t list, uint32_t ny) -> hipError_t {
+        const dim3 grid(nblk[axis], ny);
+        const uint32_t* f = first + (size_t)axis * stride;
+        for (int c = 0; c <= 10; ++c) {
+            if (!((classes[axis] >> c) & 1u)) continue;
+            switch (c) {
+            case 6: launch_pass<T, Rt, 6>(axis, grid, lds[axis], s, reps, f, nrep, list, fields, tw, sp, sample_sq, bins, bin_stride); break;
+            case 7: launch_pass<T, Rt, 7>(axis, grid, lds[axis], s, reps, f, nrep, list, fields, tw, sp, sample_sq, bins, bin_stride); break;
+            case 8: launch_pass<T, Rt, 8>(axis, grid, lds[axis], s, reps, f, nrep, list, fields, tw, sp, sample_sq, bins, bin_stride); break;
+            case 9: launch_pass<T, Rt, 9>(axis, grid, lds[axis], s, reps, f, nrep, list, fields, tw, sp, sample_sq, bins, bin_stride); break;
+            case 10: launch_pass<T, Rt, 10>(axis, grid, lds[axis], s, reps, f, nrep, list, fields, tw, sp, sample_sq, bins, bin_stride); break;
+            default: launch_pass<T, Rt, 0>(axis, grid, lds[axis], s, reps, f, nrep, list, fields, tw, sp, sample_sq, bins, bin_stride); break;
+            }
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    hipError_t e = pass(0, 0u, 1u);
+    if (order == 0) {
+        if (e == hipSuccess) e = pass(1, 0x6543210u, kFftFields);
+        if (e == hipSuccess) e = pass(2, 0x6543210u, kFftFields);
+    } else {
+        for (int g = 0; g < kFieldGroups && e == hipSuccess; ++g) {
+            e = pass(1, kGroupFields[g], kGroupFieldCount[g]);
+            if (e == hipSuccess) e = pass(2, kGroupFields[g], kGroupFieldCount[g]);
+        }
+    }
+    if (e != hipSuccess) return e;
+    spectrum_finalize_kernel<<<dim3((max_nshell * kSpec + kBlock - 1) / kBlock, nrep), kBlock, 0, s>>>(
+        reps, sample_sq, counts, bins, bin_stride, sacc);
+    return hipGetLastError();
 }
 
 hipError_t launch_spectrum(int precision, const RepDev* reps, int32_t nrep, const uint32_t* first, const uint32_t* nblk,
-                           const void* fields, const double2* tw, double2* spec, const double* sample_sq,
-                           const int64_t* counts, unsigned long long* bins, double* sacc, const size_t* lds,
+                           const void* fields, const double2* tw, void* spec, const double* sample_sq,
+                           const int64_t* counts, unsigned long long* bins, uint32_t bin_stride, double* sacc,
+                           uint32_t max_nshell, const size_t* lds, const uint32_t* classes, int order,
                            hipStream_t s)
 {
-    // first: 4 prefix arrays of nrep + 1 entries (passes x, y, z, binning); nblk: their totals
-    for (int axis = 0; axis < 3; ++axis) {
-        const dim3 grid(nblk[axis], kFftArrays);
-        const uint32_t* f = first + (size_t)axis * (nrep + 1);
-        if (precision == kFP64) {
-            const double* fl = (const double*)fields;
-            if (axis == 0) fft_pass_kernel<double, 0><<<grid, kBlock, lds[0], s>>>(reps, f, nrep, fl, tw, spec);
-            else if (axis == 1) fft_pass_kernel<double, 1><<<grid, kBlock, lds[1], s>>>(reps, f, nrep, fl, tw, spec);
-            else fft_pass_kernel<double, 2><<<grid, kBlock, lds[2], s>>>(reps, f, nrep, fl, tw, spec);
-        } else {
-            const float* fl = (const float*)fields;
-            if (axis == 0) fft_pass_kernel<float, 0><<<grid, kBlock, lds[0], s>>>(reps, f, nrep, fl, tw, spec);
-            else if (axis == 1) fft_pass_kernel<float, 1><<<grid, kBlock, lds[1], s>>>(reps, f, nrep, fl, tw, spec);
-            else fft_pass_kernel<float, 2><<<grid, kBlock, lds[2], s>>>(reps, f, nrep, fl, tw, spec);
-        }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    spectrum_bin_kernel<<<nblk[3], kBlock, lds[3], s>>>(reps, first + 3 * (size_t)(nrep + 1), nrep, spec, sample_sq,
-                                                        bins);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    spectrum_finalize_kernel<<<nrep, kBlock, 0, s>>>(reps, sample_sq, counts, bins, sacc);
-    return hipGetLastError();
+    // first: 3 prefix arrays of nrep + 1 workgroup counts (passes x, y, z); nblk: their totals
+    if (precision == kFP64)
+        return launch_spectrum_t<double, double>(reps, nrep, first, nblk, (const double*)fields, tw, spec, sample_sq,
+                                                 counts, bins, bin_stride, sacc, max_nshell, lds, classes, order, s);
+    return launch_spectrum_t<float, float>(reps, nrep, first, nblk, (const float*)fields, tw, spec, sample_sq, counts,
+                                           bins, bin_stride, sacc, max_nshell, lds, classes, order, s);
 }
 
 }  // namespace gmf

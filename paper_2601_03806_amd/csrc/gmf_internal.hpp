@@ -29,7 +29,8 @@ struct StepArgs {
     const int64_t* d_step;        // device step counter (NULL: step_base is the step)
     int64_t step_base;            // step = step_base + (d_step ? *d_step : 0)
     void* fields;                 // sampled fields (SAMPLE variants)
-    double* partials;             // unused by the step kernel (kept for the sampling kernels)
+    double* partials;             // sampling steps: one record of kPartialStride doubles per lattice
+                                  // block (FP64 sums of the observables of its nodes)
     uint32_t nblocks;             // lattice blocks (set by launch_step)
     uint32_t xcd;                 // 0: workgroup b takes lattice block b; else the number of XCDs,
                                   // each taking runs of `chunk` consecutive blocks
@@ -87,23 +88,34 @@ constexpr int mtile_threads(int t)
 hipError_t launch_step(int precision, int collision, bool sample, int sm, int grp, int npt, const StepArgs& a,
                        uint32_t nblocks, hipStream_t s);
 hipError_t launch_init(int precision, void* buf, const RepDev* rep_dev, const RepDev& rep, hipStream_t s);
-// FP64 partials of the observables from the sampled fields: nrep * kObsChunks * kPartialStride doubles
-hipError_t launch_observables(int precision, const RepDev* reps, int32_t nrep, const void* fields, double* partials,
-                              hipStream_t s);
+// FP64 partial records of the observables from the sampled fields: one per workgroup of kObsNodes
+// nodes (RepDev::obs_first, obs_blocks; first: nrep + 1 prefix sums, nblocks their total)
+hipError_t launch_observables(int precision, const RepDev* reps, int32_t nrep, const uint32_t* first,
+                              uint32_t nblocks, const void* fields, double* partials, hipStream_t s);
+// Those records summed in two fixed-order stages: slices of kBlock records (RepDev::slice_first;
+// max_slices the most slices of a replica), then one workgroup per replica updating its accumulators.
 // sample_sq (nullable): nrep * kObs sums over the box of each observable squared, for this sample
-hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* partials, double* acc,
-                               double* sample_sq, hipStream_t s);
+hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, uint32_t max_slices, const double* partials,
+                               double* slices, double* acc, double* sample_sq, hipStream_t s);
 hipError_t launch_twiddles(const RepDev* reps, int32_t nrep, double2* tw, hipStream_t s);
-// dft: per replica kFields * nz * kDftPlane complex; zbuf: nrep * kFields * kZSplit * 196 complex
-// chunks: workgroups of the first DFT stage, (replica << 16) | chunk index
-hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint32_t* chunks, uint32_t nchunks,
+// dft: per replica kFields * nz * dft_col_blocks(nx) * kDftPlane complex; zbuf: nrep * kFields * kZSplit * 196
+// complex; first: nrep + 1 prefix sums of the replicas' first-stage workgroups (dft_chunks), nchunks their total
+hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint32_t* first, uint32_t nchunks,
                       const void* fields, const double2* tw, double2* dft, double2* zbuf, double* acc, hipStream_t s);
-// full-box shell spectra of one sample (gmf_fft.hip): first = 4 prefix arrays of
-// nrep + 1 workgroup counts (passes x, y, z, binning), nblk their totals, lds
-// the dynamic LDS bytes of each of the four kernels
+// full-box shell spectra of one sample (gmf_fft.hip): first = 3 prefix arrays of
+// nrep + 1 workgroup counts (passes x, y and z with the shell sums), nblk their
+// totals, lds the dynamic LDS bytes of each of the three kernels; spec holds the
+// seven half spectra of every replica in the kernel precision (RepDev::spec_offset);
+// bins: kBinCopies copies, bin_stride = kSpec * (shells of all replicas) values apart;
+// max_nshell: the most shells of one replica;
+// classes[a]: bit c set when a replica's lines along axis a are of kernel class c
+// (fft_class: log2 of a power-of-two length 64 .. 1024, else 0);
+// order 0 runs the passes one after the other over all fields, order 1 group by
+// group (x pass of a field pair, then y and z passes of its half spectra)
 hipError_t launch_spectrum(int precision, const RepDev* reps, int32_t nrep, const uint32_t* first, const uint32_t* nblk,
-                           const void* fields, const double2* tw, double2* spec, const double* sample_sq,
-                           const int64_t* counts, unsigned long long* bins, double* sacc, const size_t* lds,
+                           const void* fields, const double2* tw, void* spec, const double* sample_sq,
+                           const int64_t* counts, unsigned long long* bins, uint32_t bin_stride, double* sacc,
+                           uint32_t max_nshell, const size_t* lds, const uint32_t* classes, int order,
                            hipStream_t s);
 hipError_t launch_set_step(int64_t* d_step, int64_t value, hipStream_t s);
 hipError_t launch_advance_step(int64_t* d_step, int64_t by, hipStream_t s);

@@ -327,81 +327,89 @@ hipError_t launch_init(int precision, void* buf, const RepDev* rep_dev, const Re
 }
 
 // ---------------------------------------------------------------------------
-// Sampling: reduction of the workgroup partials into the FP64 accumulators
-// (spatial mean, mean square and variance of each observable).  Two stages
-// with a fixed summation order: kReduceSlices workgroups per replica sum
-// contiguous slices of the partials, then one workgroup per replica adds the
-// slices and updates the accumulators.
+// Sampling: the observables of the sampled state, from the six fields the step
+// kernel wrote, summed in FP64 into the accumulators in a fixed order (so that
+// a state always gives the same bits):
+//   observables_kernel       kObsNodes consecutive nodes of one replica per
+//                            workgroup, 16 per thread, into one partial record;
+//   stats_slice_kernel       kBlock consecutive records of a replica per slice;
+//   stats_accumulate_kernel  one workgroup per replica adds its slices.
 // ---------------------------------------------------------------------------
-// Observables of the sampled state from the six fields the step kernel wrote
-// (drho, j, sum Pi_aa - 3 rho0 cs2, sum_{a<b} Pi_ab); u = j / (rho0 + drho).
-// Grid (kObsChunks, replicas): each workgroup strides over its replica's nodes
-// and writes FP64 partial sums of every observable, of its square, and the
-// count of non-finite densities.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void observables_kernel(const RepDev* reps, const T* __restrict__ fields,
-                                                             double* partials)
+__global__ __launch_bounds__(kBlock) void observables_kernel(const RepDev* reps, const uint32_t* first, int32_t nrep,
+                                                             const T* __restrict__ fields, double* partials)
 {
-    const int r = blockIdx.y;
+    const int r = replica_of_block(first, nrep, blockIdx.x);
     const RepDev R = uniform_rep(reps[r]);
-    if (blockIdx.x >= R.obs_chunks) return;
-    constexpr int NV = 2 * kObs + 1;
-    double acc[NV];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-    const T* fl = fields + R.field_offset;
     const uint64_t N = R.n;
-#pragma unroll 4
-    for (uint32_t n = blockIdx.x * kBlock + threadIdx.x; n < R.n; n += R.obs_chunks * kBlock) {
-        double o[kObs];
-        o[0] = (double)fl[n];
-        o[1] = (double)fl[N + n];
-        o[2] = (double)fl[2 * N + n];
-        o[3] = (double)fl[3 * N + n];
-        o[4] = o[1] + o[2] + o[3];
-        o[5] = (double)fl[4 * N + n];
-        o[6] = (double)fl[5 * N + n];
-        const double irho = 1.0 / (R.rho0 + o[0]);
-        o[7] = o[1] * irho;
-        o[8] = o[2] * irho;
-        o[9] = o[3] * irho;
+    const T* fl = fields + R.field_offset;
+    const T rho0 = rep_param<T>(R.rho0, R.rho0f);
+    double acc[kObsVals];
 #pragma unroll
-        for (int q = 0; q < kObs; ++q) {
-            acc[2 * q] += o[q];
-            acc[2 * q + 1] = fma(o[q], o[q], acc[2 * q + 1]);
+    for (int q = 0; q < kObsVals; ++q) acc[q] = 0.0;
+    const uint32_t n0 = (blockIdx.x - first[r]) * kObsNodes + threadIdx.x;
+    // batches of four nodes: their 24 loads are issued unconditionally (past
+    // the box end they read the last node again) before any of them is used
+    constexpr int kBatch = 4;
+    for (uint32_t k0 = 0; k0 < kObsNodes / kBlock; k0 += kBatch) {
+        T v[kBatch][kFields];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const uint32_t n = min(n0 + (k0 + u) * kBlock, R.n - 1);
+#pragma unroll
+            for (int f = 0; f < kFields; ++f) v[u][f] = fl[(uint64_t)f * N + n];
         }
-        acc[2 * kObs] += isfinite(o[0]) ? 0.0 : 1.0;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+            if (n0 + (k0 + u) * kBlock < R.n)
+                add_observables<T>(acc, rho0, v[u][0], v[u][1], v[u][2], v[u][3], v[u][4], v[u][5]);
     }
-    block_sum_store<NV>(acc, partials + ((size_t)r * kObsChunks + blockIdx.x) * kPartialStride);
+    block_sum_store<kObsVals>(acc, partials + (size_t)blockIdx.x * kPartialStride);
 }
 
-hipError_t launch_observables(int precision, const RepDev* reps, int32_t nrep, const void* fields, double* partials,
-                              hipStream_t s)
+hipError_t launch_observables(int precision, const RepDev* reps, int32_t nrep, const uint32_t* first,
+                              uint32_t nblocks, const void* fields, double* partials, hipStream_t s)
 {
-    dim3 grid(kObsChunks, nrep);
     if (precision == kFP64)
-        observables_kernel<double><<<grid, kBlock, 0, s>>>(reps, (const double*)fields, partials);
+        observables_kernel<double><<<nblocks, kBlock, 0, s>>>(reps, first, nrep, (const double*)fields, partials);
     else
-        observables_kernel<float><<<grid, kBlock, 0, s>>>(reps, (const float*)fields, partials);
+        observables_kernel<float><<<nblocks, kBlock, 0, s>>>(reps, first, nrep, (const float*)fields, partials);
     return hipGetLastError();
 }
 
-// The kObsChunks partials of each replica, summed in a fixed order, update
-// the accumulators.
-__global__ __launch_bounds__(kBlock) void stats_accumulate_kernel(const RepDev* reps, const double* partials,
+// Stage 1 of the reduction: each workgroup sums kBlock consecutive partial
+// records of one replica (blockIdx.y) into a slice record; slices past the
+// replica's count exit.
+__global__ __launch_bounds__(kBlock) void stats_slice_kernel(const RepDev* reps, const double* partials,
+                                                             double* slices)
+{
+    const RepDev R = uniform_rep(reps[blockIdx.y]);
+    const uint32_t nsl = (R.obs_blocks + kBlock - 1) / kBlock;
+    if (blockIdx.x >= nsl) return;
+    const uint32_t b = blockIdx.x * kBlock + threadIdx.x;
+    double v[kObsVals];
+#pragma unroll
+    for (int q = 0; q < kObsVals; ++q)
+        v[q] = b < R.obs_blocks ? partials[(size_t)(R.obs_first + b) * kPartialStride + q] : 0.0;
+    block_sum_store<kObsVals>(v, slices + (size_t)(R.slice_first + blockIdx.x) * kPartialStride);
+}
+
+// Stage 2: the slices of each replica, summed in a fixed order, update the
+// accumulators (spatial mean, mean square and variance of each observable).
+__global__ __launch_bounds__(kBlock) void stats_accumulate_kernel(const RepDev* reps, const double* slices,
                                                                   double* acc, double* sample_sq)
 {
     const RepDev& R = reps[blockIdx.x];
-    constexpr int NV = 2 * kObs + 1;
-    double v[NV];
-    for (int q = 0; q < NV; ++q) v[q] = 0.0;
-    for (uint32_t c = threadIdx.x; c < R.obs_chunks; c += kBlock) {
-        const double* p = partials + ((size_t)blockIdx.x * kObsChunks + c) * kPartialStride;
+    const uint32_t nsl = (R.obs_blocks + kBlock - 1) / kBlock;
+    double v[kObsVals];
+    for (int q = 0; q < kObsVals; ++q) v[q] = 0.0;
+    for (uint32_t c = threadIdx.x; c < nsl; c += kBlock) {
+        const double* p = slices + (size_t)(R.slice_first + c) * kPartialStride;
 #pragma unroll
-        for (int q = 0; q < NV; ++q) v[q] += p[q];
+        for (int q = 0; q < kObsVals; ++q) v[q] += p[q];
     }
-    __shared__ double tot[NV];
-    block_sum_store<NV>(v, tot);
+    __shared__ double tot[kObsVals];
+    block_sum_store<kObsVals>(v, tot);
     __syncthreads();
     if (threadIdx.x == 0) {
         double* A = acc + (size_t)blockIdx.x * kAccStride;
@@ -420,10 +428,13 @@ __global__ __launch_bounds__(kBlock) void stats_accumulate_kernel(const RepDev* 
     }
 }
 
-hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* partials, double* acc,
-                               double* sample_sq, hipStream_t s)
+hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, uint32_t max_slices, const double* partials,
+                               double* slices, double* acc, double* sample_sq, hipStream_t s)
 {
-    stats_accumulate_kernel<<<nrep, kBlock, 0, s>>>(reps, partials, acc, sample_sq);
+    stats_slice_kernel<<<dim3(max_slices, nrep), kBlock, 0, s>>>(reps, partials, slices);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    stats_accumulate_kernel<<<nrep, kBlock, 0, s>>>(reps, slices, acc, sample_sq);
     return hipGetLastError();
 }
 
@@ -432,10 +443,11 @@ hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, const double* p
 // {1,2,3,4,5,6,8,9}).  A real field has |m(-k)| = |m(k)|, so only n_x >= 0 is
 // computed and n_x > 0 counts twice.  Twiddles e^{2 pi i m / L} for the three
 // box lengths of each replica are tabulated once (twiddle_kernel).
-//   Stage 1 (workgroups of z planes, per field): DFT along y at n_y = 0..3,
-//     one column per thread (Y(-n_y) = conj Y(n_y)), then along x at
-//     n_x = 0..3 from the columns kept in LDS.
-//   Stage 2 (per replica, field and z chunk): DFT along z at n_z = -3..3.
+//   Stage 1 (workgroups of 64 columns (x, z), per field): DFT along y at
+//     n_y = 0..3 (Y(-n_y) = conj Y(n_y)), then along x at n_x = 0..3 from the
+//     columns kept in LDS, one partial record per plane and column block.
+//   Stage 2 (per replica, field and z chunk): the column blocks of each plane
+//     summed, then the DFT along z at n_z = -3..3.
 //   Stage 3 (one workgroup per replica): powers of the five spectra, shell
 //     averages into the accumulators (fixed summation order).
 // ---------------------------------------------------------------------------
@@ -460,127 +472,130 @@ hipError_t launch_twiddles(const RepDev* reps, int32_t nrep, double2* tw, hipStr
     return hipGetLastError();
 }
 
-// Partial x-transform of item o = (n_x, n_y) over columns xb .. xe - 1 whose
-// y-transforms Y[x - xb][0..3] are in Yp: sum_x Y_{n_y}(x) e^{-2 pi i n_x x / nx},
-// with Y_{-n_y} = conj(Y_{n_y}).  twx[m] = e^{2 pi i m / nx}.
-__device__ __forceinline__ double2 dft_x_item(const double2* Yp, const double2* twx, uint32_t nx, uint32_t xb,
-                                              uint32_t xe, uint32_t o)
-{
-    const uint32_t q = o / kDftNy;
-    const int sy = (int)(o % kDftNy) - 3;
-    const uint32_t ay = (uint32_t)(sy < 0 ? -sy : sy);
-    const double sg = sy < 0 ? -1.0 : 1.0;          // conjugate for negative n_y
-    double re = 0.0, im = 0.0;
-    uint32_t m = (uint32_t)(((uint64_t)q * xb) % nx);
-    for (uint32_t x = xb; x < xe; ++x) {
-        const double2 yv = Yp[(uint64_t)(x - xb) * 4 + ay];
-        const double yr = yv.x, yi = sg * yv.y;
-        const double2 t = twx[m];
-        // (yr + i yi)(c - i s)
-        re += yr * t.x + yi * t.y;
-        im += yi * t.x - yr * t.y;
-        m += q;
-        while (m >= nx) m -= nx;
-    }
-    return make_double2(re, im);
-}
-
-// One workgroup of the first stage.  twx / twy point either into LDS or into
-// the twiddle tables in memory; the caller branches once so that each path
-// keeps a single address space (no generic loads in the inner loops).
+// Stage 1, one workgroup per (chunk, field): the y-transform at n_y = 0..3 of
+// the chunk's 64 columns (lane = column), the y range split over the four
+// wavefronts so that each thread issues ny / 4 loads of its column, eight at a
+// time; the wavefronts' sums meet in LDS; then the x-transform at n_x = 0..3 of
+// each plane's columns in the chunk: the 28 items (n_x, n_y = -3..3, using
+// Y(-n_y) = conj(Y(n_y)) of a real column) of each plane, eight threads per item
+// with a fixed-order shuffle sum, into the partial record of (plane, column
+// block).  twx[m] = e^{2 pi i m / nx}, twy[m] = e^{2 pi i m / ny} in memory:
+// the y loop's twiddle indices are uniform, so its twiddles come through
+// scalar loads.
 template <typename T>
-__device__ __forceinline__ void dft_plane_body(const RepDev& R, uint32_t z0, int fld, const T* __restrict__ fields,
-                                               const double2* twx, const double2* twy, double2* Ys, double2* dft)
+__device__ __forceinline__ void dft_plane_body(const RepDev& R, uint32_t chunk, int fld, const T* __restrict__ fields,
+                                               const double2* __restrict__ twx, const double2* __restrict__ twy,
+                                               double2 (*Ys)[kDftCols][4], double2 (*Tx)[kDftCols], double2* dft)
 {
     const uint32_t nx = R.nx, ny = R.ny, nz = R.nz;
-    const uint32_t P = dft_planes_per_block(nx);
-    const T* src = fields + R.field_offset + (uint64_t)fld * R.n;
-    // Several planes per workgroup (nx <= kBlock / 2): one pass over all their
-    // columns.  One plane per workgroup: the columns come in passes of kBlock,
-    // and the 28 items (n_x, n_y) of the plane, owned by threads 0..27,
-    // accumulate over the passes in x order.  The LDS use does not depend on
-    // the box.
-    const uint32_t cols = P * nx;
-    const uint32_t pass_cols = P == 1 ? (uint32_t)kBlock : cols;
-    double acc_re = 0.0, acc_im = 0.0;
-    for (uint32_t c0 = 0; c0 < cols; c0 += pass_cols) {
-        // y first: one column per thread, coalesced across lanes; n_y = 0..3
-        // (a real column has Y(-n_y) = conj(Y(n_y))); the twiddle index is the
-        // same for every lane
-        const uint32_t c = c0 + threadIdx.x;
-        if (threadIdx.x < pass_cols && c < cols) {
-            const uint32_t p = c / nx, x = c % nx, z = z0 + p;
-            double y0 = 0.0, y1r = 0.0, y1i = 0.0, y2r = 0.0, y2i = 0.0, y3r = 0.0, y3i = 0.0;
-            if (z < nz) {
-                const T* col = src + (uint64_t)z * nx * ny + x;
-                uint32_t m2 = 0, m3 = 0;
-                for (uint32_t y = 0; y < ny; ++y) {
-                    const double v = (double)col[(uint64_t)y * nx];
-                    const double2 t1 = twy[y], t2 = twy[m2], t3 = twy[m3];
-                    y0 += v;
-                    y1r = fma(v, t1.x, y1r);
-                    y1i = fma(-v, t1.y, y1i);
-                    y2r = fma(v, t2.x, y2r);
-                    y2i = fma(-v, t2.y, y2i);
-                    y3r = fma(v, t3.x, y3r);
-                    y3i = fma(-v, t3.y, y3i);
-                    m2 += 2;
-                    while (m2 >= ny) m2 -= ny;
-                    m3 += 3;
-                    while (m3 >= ny) m3 -= ny;
-                }
-            }
-            double2* Yc = Ys + (uint64_t)threadIdx.x * 4;
-            Yc[0] = make_double2(y0, 0.0);
-            Yc[1] = make_double2(y1r, y1i);
-            Yc[2] = make_double2(y2r, y2i);
-            Yc[3] = make_double2(y3r, y3i);
-        }
-        __syncthreads();
-        // then x over this pass's columns: item = (plane, n_x, n_y)
-        if (P > 1) {
-            // several planes, one pass: every item is finished here
-            for (uint32_t it = threadIdx.x; it < P * kDftPlane; it += kBlock) {
-                const uint32_t p = it / kDftPlane, o = it % kDftPlane;
-                const uint32_t z = z0 + p;
-                if (z >= nz) continue;
-                const double2 v = dft_x_item(Ys + (uint64_t)p * nx * 4, twx, nx, 0u, nx, o);
-                dft[R.dft_offset + ((uint64_t)fld * nz + z) * kDftPlane + o] = v;
-            }
-        } else if (threadIdx.x < kDftPlane) {
-            const double2 v = dft_x_item(Ys, twx, nx, c0, min(nx, c0 + (uint32_t)kBlock), threadIdx.x);
-            acc_re += v.x;
-            acc_im += v.y;
-        }
-        __syncthreads();
+    const uint32_t CB = dft_col_blocks(nx), P = dft_planes_per_chunk(nx);
+    const bool wide = nx >= kDftCols;
+    const uint32_t z0 = wide ? chunk / CB : chunk * P;
+    const uint32_t cb = wide ? chunk - z0 * CB : 0u;
+    // the wavefront index is uniform: the y loop, its twiddle indices and loads stay scalar
+    const uint32_t lane = threadIdx.x & 63u, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // this lane's column: plane z0 + p, x; lanes without a column read the
+    // chunk's first column (the loads stay unconditional) and add zero
+    const uint32_t p = wide ? 0u : lane / nx;
+    const uint32_t x = wide ? cb * kDftCols + lane : lane - p * nx;
+    const bool valid = wide ? x < nx : (p < P && z0 + p < nz);
+    const T* col = fields + R.field_offset + (uint64_t)fld * R.n +
+                   (valid ? (uint64_t)(z0 + p) * nx * ny + x : (uint64_t)z0 * nx * ny + cb * kDftCols);
+    const double keep = valid ? 1.0 : 0.0;
+    // the x twiddles e^{2 pi i q x / nx} (q = 1..3) of the chunk's columns, for
+    // the x-transform below; their loads overlap the y loop
+    if (threadIdx.x < 3 * kDftCols) {
+        const uint32_t q = threadIdx.x / kDftCols + 1, c = threadIdx.x % kDftCols;
+        const uint32_t xc = wide ? min(cb * kDftCols + c, nx - 1) : c % nx;
+        Tx[q - 1][c] = twx[(uint32_t)(((uint64_t)q * xc) % nx)];
     }
-    if (P == 1 && threadIdx.x < kDftPlane && z0 < nz)
-        dft[R.dft_offset + ((uint64_t)fld * nz + z0) * kDftPlane + threadIdx.x] = make_double2(acc_re, acc_im);
+    // this wavefront's rows
+    const uint32_t yq = (ny + 3) / 4;
+    const uint32_t ylo = min(ny, wave * yq), yhi = min(ny, ylo + yq);
+    double y0 = 0.0, y1r = 0.0, y1i = 0.0, y2r = 0.0, y2i = 0.0, y3r = 0.0, y3i = 0.0;
+    auto add = [&](double v, uint32_t y) {
+        // 2y mod ny and 3y mod ny for y < ny, without loop-carried state
+        const uint32_t m2 = 2 * y - (2 * y >= ny ? ny : 0u);
+        const uint32_t m3 = 3 * y - ny * ((3 * y >= ny ? 1u : 0u) + (3 * y >= 2 * ny ? 1u : 0u));
+        const double2 t1 = twy[y], t2 = twy[m2], t3 = twy[m3];
+        y0 += v;
+        y1r = fma(v, t1.x, y1r);
+        y1i = fma(-v, t1.y, y1i);
+        y2r = fma(v, t2.x, y2r);
+        y2i = fma(-v, t2.y, y2i);
+        y3r = fma(v, t3.x, y3r);
+        y3i = fma(-v, t3.y, y3i);
+    };
+    uint32_t y = ylo;
+    for (; y + 8 <= yhi; y += 8) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = col[(uint64_t)(y + u) * nx];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) add(keep * (double)v[u], y + u);
+    }
+    for (; y < yhi; ++y) add(keep * (double)col[(uint64_t)y * nx], y);
+    Ys[wave][lane][0] = make_double2(y0, 0.0);
+    Ys[wave][lane][1] = make_double2(y1r, y1i);
+    Ys[wave][lane][2] = make_double2(y2r, y2i);
+    Ys[wave][lane][3] = make_double2(y3r, y3i);
+    __syncthreads();
+    {
+        // the four wavefronts' sums, in wavefront order, into Ys[0]
+        const uint32_t c = threadIdx.x & 63u, k = threadIdx.x >> 6;
+        double2 s = Ys[0][c][k];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) s = make_double2(s.x + Ys[w][c][k].x, s.y + Ys[w][c][k].y);
+        Ys[0][c][k] = s;
+    }
+    __syncthreads();
+    // x-transform: item it = (plane pp, n_x, n_y); group g of eight threads per item
+    const uint32_t g = threadIdx.x >> 3, sub = threadIdx.x & 7u;
+    const uint32_t nitems = (wide ? 1u : P) * (uint32_t)kDftPlane;
+    const uint32_t ncols = wide ? min(kDftCols, nx - cb * kDftCols) : nx;
+    for (uint32_t base = 0; base < nitems; base += kBlock / 8) {
+        const uint32_t it = base + g;
+        const bool act = it < nitems;
+        const uint32_t pp = act ? it / kDftPlane : 0u, o = act ? it % kDftPlane : 0u;
+        const uint32_t q = o / kDftNy;
+        const int sy = (int)(o % kDftNy) - 3;
+        const uint32_t ay = (uint32_t)(sy < 0 ? -sy : sy);
+        const double sg = sy < 0 ? -1.0 : 1.0;          // conjugate for negative n_y
+        double re = 0.0, im = 0.0;
+        if (act) {
+            for (uint32_t c = sub; c < ncols; c += 8) {
+                const double2 yv = Ys[0][wide ? c : pp * nx + c][ay];
+                const double yr = yv.x, yi = sg * yv.y;
+                const double2 t = q == 0 ? make_double2(1.0, 0.0) : Tx[q - 1][c];
+                // (yr + i yi)(c - i s)
+                re += yr * t.x + yi * t.y;
+                im += yi * t.x - yr * t.y;
+            }
+        }
+#pragma unroll
+        for (int off = 4; off > 0; off >>= 1) {
+            re += __shfl_xor(re, off, 64);
+            im += __shfl_xor(im, off, 64);
+        }
+        if (act && sub == 0 && z0 + pp < nz)
+            dft[R.dft_offset + (((uint64_t)fld * nz + z0 + pp) * CB + cb) * kDftPlane + o] = make_double2(re, im);
+    }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void dft_plane_kernel(const RepDev* reps, const uint32_t* chunks,
+__global__ __launch_bounds__(kBlock) void dft_plane_kernel(const RepDev* reps, const uint32_t* first, int32_t nrep,
                                                            const T* __restrict__ fields,
                                                            const double2* __restrict__ tw, double2* dft)
 {
-    // Y[column][n_y = 0..3] of up to kBlock columns (one per thread), and the
-    // twiddles of both axes when they fit (else they are read from memory)
-    constexpr uint32_t kTwCache = 512;   // 8 KiB: with Ys, 24 KiB per workgroup (six per CU)
-    __shared__ double2 Ys[kBlock * 4];
-    __shared__ double2 tw_s[kTwCache];
-    const uint32_t ck = chunks[blockIdx.x];
-    const int fld = blockIdx.y;
-    const int r = (int)(ck >> 16);
+    // Y[wavefront][column][n_y = 0..3] (16 KiB) and the x twiddles of the chunk (3 KiB)
+    __shared__ double2 Ys[4][kDftCols][4];
+    __shared__ double2 Tx[3][kDftCols];
+    const int r = replica_of_block(first, nrep, blockIdx.x);
     const RepDev R = uniform_rep(reps[r]);
-    const uint32_t z0 = (ck & 0xffffu) * dft_planes_per_block(R.nx);
+    const uint32_t chunk = blockIdx.x - first[r];
+    const int fld = blockIdx.y;
     const double2* twg = tw + R.tw_offset;            // e^{2 pi i m / nx}, then e^{2 pi i m / ny}
-    if (R.nx + R.ny <= kTwCache) {
-        for (uint32_t m = threadIdx.x; m < R.nx + R.ny; m += kBlock) tw_s[m] = twg[m];
-        __syncthreads();
-        dft_plane_body<T>(R, z0, fld, fields, tw_s, tw_s + R.nx, Ys, dft);
-    } else {
-        dft_plane_body<T>(R, z0, fld, fields, twg, twg + R.nx, Ys, dft);
-    }
+    dft_plane_body<T>(R, chunk, fld, fields, twg, twg + R.nx, Ys, Tx, dft);
 }
 
 __device__ __forceinline__ int shell_of(int n2)
@@ -623,10 +638,16 @@ __global__ __launch_bounds__(kBlock) void dft_z_kernel(const RepDev* reps, const
     const uint32_t z0 = min(nz, zs * per), z1 = min(nz, z0 + per);
     uint32_t m = (uint32_t)(((uint64_t)step * z0) % nz);
     double zr = 0.0, zi = 0.0;
-    const double2* P = dft + R.dft_offset + (uint64_t)fld * nz * kDftPlane + col;
-#pragma unroll 8
+    const uint32_t CB = dft_col_blocks(R.nx);
+    const double2* P = dft + R.dft_offset + (uint64_t)fld * nz * CB * kDftPlane + col;
+#pragma unroll 4
     for (uint32_t z = z0; z < z1; ++z) {
-        const double2 p = P[(uint64_t)z * kDftPlane];
+        // the plane's partial records of its column blocks, in block order
+        double2 p = P[(uint64_t)z * CB * kDftPlane];
+        for (uint32_t cb = 1; cb < CB; ++cb) {
+            const double2 pc = P[((uint64_t)z * CB + cb) * kDftPlane];
+            p = make_double2(p.x + pc.x, p.y + pc.y);
+        }
         const double2 t = twz[m];
         zr += p.x * t.x + p.y * t.y;
         zi += p.y * t.x - p.x * t.y;
@@ -683,14 +704,14 @@ __global__ __launch_bounds__(kBlock) void dft_shell_kernel(const RepDev* reps, c
     }
 }
 
-hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint32_t* chunks, uint32_t nchunks,
+hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint32_t* first, uint32_t nchunks,
                       const void* fields, const double2* tw, double2* dft, double2* zbuf, double* acc, hipStream_t s)
 {
     dim3 grid(nchunks, kFields);
     if (precision == kFP64)
-        dft_plane_kernel<double><<<grid, kBlock, 0, s>>>(reps, chunks, (const double*)fields, tw, dft);
+        dft_plane_kernel<double><<<grid, kBlock, 0, s>>>(reps, first, nrep, (const double*)fields, tw, dft);
     else
-        dft_plane_kernel<float><<<grid, kBlock, 0, s>>>(reps, chunks, (const float*)fields, tw, dft);
+        dft_plane_kernel<float><<<grid, kBlock, 0, s>>>(reps, first, nrep, (const float*)fields, tw, dft);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dft_z_kernel<<<dim3(nrep, kFields, kZSplit), kBlock, 0, s>>>(reps, tw, dft, zbuf);

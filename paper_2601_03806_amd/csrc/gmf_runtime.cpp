@@ -62,16 +62,19 @@ const int kShellCnt[kShells] = {6, 12, 8, 6, 24, 24, 12, 30};
 struct Layout {
     size_t pop_bytes = 0, popA = 0, popB = 0;   // popB == popA: one buffer (AA only)
     size_t reps = 0, blk2rep = 0, step = 0, acc = 0, tot = 0, mpart = 0;
-    size_t fields = 0, partials = 0, dft = 0, chunks = 0, stage = 0, stage_bytes = 0, total = 0;
-    uint32_t total_chunks = 0;     // workgroups of the first spectrum stage
+    size_t fields = 0, partials = 0, slices = 0, obs_first = 0, dft = 0, chunks = 0, stage = 0, stage_bytes = 0,
+           total = 0;
+    uint64_t obs_blocks = 0, obs_slices = 0;   // observables workgroups and their slices (sampling)
+    uint32_t total_chunks = 0;     // workgroups of the first DFT stage of the shell spectra
     size_t twiddles = 0, zbuf = 0;
     size_t sample_sq = 0;          // per-sample sums of squares (sampling)
     // full-box spectra (spectrum option)
     bool spectrum = false;
     size_t spec = 0, sbins = 0, sacc = 0, scounts = 0, sfirst = 0;
     uint64_t nshell_total = 0;
-    uint32_t spec_blocks[4] = {0, 0, 0, 0};   // workgroups of the x, y, z passes and of the binning
-    size_t spec_lds[4] = {0, 0, 0, 0};
+    uint32_t max_nshell = 0;        // most shells of one replica
+    uint32_t spec_blocks[3] = {0, 0, 0};   // workgroups of the x, y and z (with shell sums) passes
+    size_t spec_lds[3] = {0, 0, 0};
     uint32_t tw_complex = 0;
     uint64_t total_nodes = 0;
     uint32_t max_blocks = 0;     // lattice grid at one node per thread
@@ -160,19 +163,23 @@ int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
             FftPlan pl;
             if (!fft_plan((uint32_t)R.nx, pl) || !fft_plan((uint32_t)R.ny, pl) || !fft_plan((uint32_t)R.nz, pl))
                 return GMF_EINVAL;
+            // every pass's tile (with the z pass's shell bins) within one CU's LDS
+            const uint32_t cb = 2u * (uint32_t)es, ns = box_shells((uint32_t)R.nx, (uint32_t)R.ny, (uint32_t)R.nz);
+            for (int a = 0; a < 3; ++a)
+                if (fft_lds_bytes(a, (uint32_t)R.nx, (uint32_t)R.ny, (uint32_t)R.nz, cb, ns) > kLdsBytes)
+                    return GMF_EINVAL;
         }
     }
     if (choose_mode(reps, nrep, es, 1) < 0) return GMF_EINVAL;
     // sampling: the first DFT stage's work list packs (replica, chunk) into 16
     // bits each, and the plane sums of all replicas sit at 32-bit offsets
     if (opt && opt->sample_every > 0) {
-        uint64_t dft = 0;
+        uint64_t dft = 0, chunks = 0;
         for (int r = 0; r < nrep; ++r) {
-            const uint32_t P = dft_planes_per_block((uint32_t)reps[r].nx);
-            if (((uint64_t)reps[r].nz + P - 1) / P > (1ull << 16)) return GMF_EINVAL;
-            dft += (uint64_t)kFields * reps[r].nz * kDftPlane;
+            dft += (uint64_t)kFields * reps[r].nz * dft_col_blocks((uint32_t)reps[r].nx) * kDftPlane;
+            chunks += dft_chunks((uint32_t)reps[r].nx, (uint32_t)reps[r].nz);
         }
-        if (dft >= (1ull << 32)) return GMF_EINVAL;
+        if (dft >= (1ull << 32) || chunks >= (1ull << 31)) return GMF_EINVAL;
     }
     // workgroup and tile counts of the whole context are 32-bit: fewer than
     // 2^32 nodes in all (far beyond any device memory) keeps every one in range
@@ -194,11 +201,13 @@ Layout plan(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         L.total_nodes += n;
         L.max_blocks += (uint32_t)((n + kBlock - 1) / kBlock);
         L.total_planes += (uint32_t)reps[r].nz;
+        L.total_chunks += (uint32_t)dft_chunks((uint32_t)reps[r].nx, (uint32_t)reps[r].nz);
+        L.dft_complex += (uint32_t)(kFields * reps[r].nz * dft_col_blocks((uint32_t)reps[r].nx) * kDftPlane);
         {
-            const uint32_t P = dft_planes_per_block((uint32_t)reps[r].nx);
-            L.total_chunks += ((uint32_t)reps[r].nz + P - 1) / P;
+            const uint64_t ob = (n + kObsNodes - 1) / kObsNodes;
+            L.obs_blocks += ob;
+            L.obs_slices += (ob + kBlock - 1) / kBlock;
         }
-        L.dft_complex += (uint32_t)(kFields * reps[r].nz * kDftPlane);
         L.tw_complex += (uint32_t)(reps[r].nx + reps[r].ny + reps[r].nz);
         L.max_nx = std::max(L.max_nx, (int)reps[r].nx);
         L.max_ny = std::max(L.max_ny, (int)reps[r].ny);
@@ -242,31 +251,37 @@ Layout plan(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
     L.mpart = take(sizeof(double) * 4 * L.max_chunk_blocks);
     if (L.sampling) {
         L.fields = take((size_t)L.total_nodes * kFields * es);
-        L.partials = take(sizeof(double) * kPartialStride * kObsChunks * nrep);
+        // one record per workgroup of observables_kernel, and their slices of kBlock records
+        L.partials = take(sizeof(double) * kPartialStride * L.obs_blocks);
+        L.slices = take(sizeof(double) * kPartialStride * L.obs_slices);
+        L.obs_first = take(sizeof(uint32_t) * ((size_t)nrep + 1));
         L.dft = take(sizeof(double) * 2 * L.dft_complex);
-        L.chunks = take(sizeof(uint32_t) * L.total_chunks);
+        L.chunks = take(sizeof(uint32_t) * ((size_t)nrep + 1));   // prefix sums of the first-stage workgroups
         L.twiddles = take(sizeof(double) * 2 * L.tw_complex);
         L.zbuf = take(sizeof(double) * 2 * kFields * kZSplit * 196 * nrep);
         L.sample_sq = take(sizeof(double) * kObs * nrep);
     }
     L.spectrum = L.sampling && opt->spectrum;
     if (L.spectrum) {
+        // half spectra of the six fields and of jsum in the kernel precision: complex of 2 es bytes
+        const uint32_t cb = 2u * (uint32_t)es;
+        uint64_t half_values = 0;
         for (int r = 0; r < nrep; ++r) {
             const uint32_t nx = (uint32_t)reps[r].nx, ny = (uint32_t)reps[r].ny, nz = (uint32_t)reps[r].nz;
             const uint32_t ns = box_shells(nx, ny, nz);
             L.nshell_total += ns;
+            L.max_nshell = std::max(L.max_nshell, ns);
             for (int a = 0; a < 3; ++a) {
-                L.spec_blocks[a] += fft_tiles(a, nx, ny, nz);
-                L.spec_lds[a] = std::max<size_t>(L.spec_lds[a], fft_lds_bytes(a, nx, ny, nz));
+                L.spec_blocks[a] += fft_tiles(a, nx, ny, nz, cb);
+                L.spec_lds[a] = std::max<size_t>(L.spec_lds[a], fft_lds_bytes(a, nx, ny, nz, cb, ns));
             }
-            L.spec_blocks[3] += (uint32_t)((bin_nodes(nx, ny, nz) + kBinPoints - 1) / kBinPoints);
-            L.spec_lds[3] = std::max<size_t>(L.spec_lds[3], sizeof(unsigned long long) * kSpec * ns);
+            half_values += (uint64_t)kFftFields * half_stride(nx) * ny * nz;
         }
-        L.spec = take(sizeof(double) * 2 * kFftArrays * (size_t)L.total_nodes);
-        L.sbins = take(sizeof(unsigned long long) * kSpec * L.nshell_total);
+        L.spec = take((size_t)cb * half_values);
+        L.sbins = take(sizeof(unsigned long long) * kSpec * kBinCopies * L.nshell_total);
         L.sacc = take(sizeof(double) * kSpec * L.nshell_total);
         L.scounts = take(sizeof(int64_t) * L.nshell_total);
-        L.sfirst = take(sizeof(uint32_t) * 4 * (nrep + 1));
+        L.sfirst = take(sizeof(uint32_t) * 3 * (nrep + 1));
     }
     L.stage = take(L.stage_bytes);
     L.total = off;
@@ -319,9 +334,13 @@ struct gmf_ctx {
     int mtile = kDefaultMTile;     // moment storage: tile shape (index into kMTileX/Y)
     uint32_t mtz = kDefaultMTz;    // moment storage: z planes per tile
     uint32_t xcd_count = 1;        // XCDs of the device
+    int fft_order = 1;             // spectrum passes group by group (1) or pass by pass (0)
+    uint32_t fft_classes[3] = {0, 0, 0};   // per axis: bit c set when a replica's lines are of kernel class c
     int xcd_map = 0;               // workgroup mapping: 0 linear, else an index into kXcdChunks
     uint32_t occ = 0;              // population step: workgroups per CU cap (kOccCap; 0: none)
     uint32_t nblocks = 0;          // lattice grid for the current npt
+    uint32_t obs_total = 0;        // workgroups of observables_kernel (sampling)
+    uint32_t max_slices = 0;       // most statistics slices of one replica (sampling)
     int graph_steps = 0;           // longest captured step loop; 0: direct launches
     int64_t step = 0;
     bool dev_step_valid = false;   // device counter == step
@@ -343,12 +362,14 @@ struct gmf_ctx {
     double* d_mpart() { return reinterpret_cast<double*>(ws + L.mpart); }
     void* d_fields() { return L.sampling ? ws + L.fields : nullptr; }
     double* d_partials() { return L.sampling ? reinterpret_cast<double*>(ws + L.partials) : nullptr; }
+    double* d_slices() { return L.sampling ? reinterpret_cast<double*>(ws + L.slices) : nullptr; }
+    uint32_t* d_obs_first() { return L.sampling ? reinterpret_cast<uint32_t*>(ws + L.obs_first) : nullptr; }
     double* d_dft() { return L.sampling ? reinterpret_cast<double*>(ws + L.dft) : nullptr; }
     uint32_t* d_chunks() { return L.sampling ? reinterpret_cast<uint32_t*>(ws + L.chunks) : nullptr; }
     double2* d_twiddles() { return L.sampling ? reinterpret_cast<double2*>(ws + L.twiddles) : nullptr; }
     double2* d_zbuf() { return L.sampling ? reinterpret_cast<double2*>(ws + L.zbuf) : nullptr; }
     double* d_sample_sq() { return L.sampling ? reinterpret_cast<double*>(ws + L.sample_sq) : nullptr; }
-    double2* d_spec() { return reinterpret_cast<double2*>(ws + L.spec); }
+    void* d_spec() { return ws + L.spec; }
     unsigned long long* d_sbins() { return reinterpret_cast<unsigned long long*>(ws + L.sbins); }
     double* d_sacc() { return reinterpret_cast<double*>(ws + L.sacc); }
     int64_t* d_scounts() { return reinterpret_cast<int64_t*>(ws + L.scounts); }
@@ -431,17 +452,19 @@ int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
         CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, step_pattern(ctx, t), ctx->mode, ctx->npt, a,
                        ctx->nblocks, ctx->stream));
     if (sample) {
-        CK(launch_observables(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_fields(), ctx->d_partials(),
-                              ctx->stream));
-        CK(launch_stats_reduce(ctx->d_reps(), ctx->nrep, ctx->d_partials(), ctx->d_acc(), ctx->d_sample_sq(),
-                               ctx->stream));
+        CK(launch_observables(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_obs_first(), ctx->obs_total,
+                              ctx->d_fields(), ctx->d_partials(), ctx->stream));
+        CK(launch_stats_reduce(ctx->d_reps(), ctx->nrep, ctx->max_slices, ctx->d_partials(), ctx->d_slices(),
+                               ctx->d_acc(), ctx->d_sample_sq(), ctx->stream));
         CK(launch_dft(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_chunks(), ctx->L.total_chunks,
                       ctx->d_fields(), ctx->d_twiddles(), reinterpret_cast<double2*>(ctx->d_dft()), ctx->d_zbuf(),
                       ctx->d_acc(), ctx->stream));
         if (ctx->L.spectrum)
             CK(launch_spectrum(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_sfirst(), ctx->L.spec_blocks,
                                ctx->d_fields(), ctx->d_twiddles(), ctx->d_spec(), ctx->d_sample_sq(),
-                               ctx->d_scounts(), ctx->d_sbins(), ctx->d_sacc(), ctx->L.spec_lds, ctx->stream));
+                               ctx->d_scounts(), ctx->d_sbins(), (uint32_t)(kSpec * ctx->L.nshell_total), ctx->d_sacc(),
+                               ctx->L.max_nshell, ctx->L.spec_lds, ctx->fft_classes,
+                               ctx->fft_order, ctx->stream));
     }
     return GMF_OK;
 }
@@ -930,12 +953,24 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         if (ctx->xcd_count > 1 && strcmp(forced, "xcd") == 0) ctx->xcd_map = 1;
         if (ctx->xcd_count > 1 && strcmp(forced, "xcd16") == 0) ctx->xcd_map = 2;
     }
+    // spectrum kernel classes present along each axis
+    for (int r = 0; r < nrep; ++r) {
+        ctx->fft_classes[0] |= 1u << fft_class((uint32_t)reps[r].nx);
+        ctx->fft_classes[1] |= 1u << fft_class((uint32_t)reps[r].ny);
+        ctx->fft_classes[2] |= 1u << fft_class((uint32_t)reps[r].nz);
+    }
+    // GMF_FFT_ORDER = 0 | 1 forces the order of the spectrum passes (tests)
+    if (const char* forced = getenv("GMF_FFT_ORDER")) {
+        const int k = atoi(forced);
+        if (k == 0 || k == 1) ctx->fft_order = k;
+    }
     // replica records
     uint64_t pop_off = 0, field_off = 0, spec_off = 0;
-    uint32_t dft_off = 0, tw_off = 0, shell_off = 0;
-    std::vector<uint32_t> chunks;
+    uint32_t dft_off = 0, tw_off = 0, shell_off = 0, slice_off = 0;
+    std::vector<uint32_t> obs_first(1, 0u);   // prefix sums of the observables workgroups
+    std::vector<uint32_t> chunks(1, 0u);   // prefix sums of the first DFT stage's workgroups
     std::vector<int64_t> shell_counts;
-    std::vector<uint32_t> spec_first(L.spectrum ? 4 * (size_t)(nrep + 1) : 0, 0u);
+    std::vector<uint32_t> spec_first(L.spectrum ? 3 * (size_t)(nrep + 1) : 0, 0u);
     for (int r = 0; r < nrep; ++r) {
         const gmf_replica& in = reps[r];
         RepDev R;
@@ -950,12 +985,18 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         R.field_offset = field_off;
         R.dft_offset = dft_off;
         R.tw_offset = tw_off;
-        // observables reduction: at least 16 nodes per thread, at most kObsChunks workgroups
-        R.obs_chunks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kObsChunks, R.n / (16u * kBlock)));
+        // observables reduction: workgroups of kObsNodes nodes, slices of kBlock of their records
+        R.obs_first = ctx->obs_total;
+        R.obs_blocks = (R.n + kObsNodes - 1) / kObsNodes;
+        R.slice_first = slice_off;
+        ctx->obs_total += R.obs_blocks;
+        slice_off += (R.obs_blocks + kBlock - 1) / kBlock;
+        ctx->max_slices = std::max(ctx->max_slices, (R.obs_blocks + kBlock - 1) / kBlock);
+        obs_first.push_back(ctx->obs_total);
         tw_off += R.nx + R.ny + R.nz;
         pop_off += (uint64_t)(ctx->mom ? kMom : Q) * R.n;
         field_off += (uint64_t)kFields * R.n;
-        dft_off += (uint32_t)(kFields * R.nz * kDftPlane);
+        dft_off += (uint32_t)(kFields * R.nz * dft_col_blocks(R.nx) * kDftPlane);
         R.key0 = (uint32_t)in.seed;
         R.key1 = (uint32_t)(in.seed >> 32);
         R.noise_on = in.kbt > 0.0 ? 1u : 0u;
@@ -974,28 +1015,26 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         R.omegaf = (float)R.omega;
         R.one_m_omegaf = (float)R.one_m_omega;
         if (L.spectrum) {
+            const uint32_t cb = opt.precision == GMF_FP32_SHIFTED ? 8u : 16u;   // complex value of the kernels
             R.spec_offset = spec_off;
             R.shell_offset = shell_off;
             R.nshell = box_shells(R.nx, R.ny, R.nz);
-            spec_off += (uint64_t)kFftArrays * R.n;
+            spec_off += (uint64_t)kFftFields * half_stride(R.nx) * R.ny * R.nz;
             shell_off += R.nshell;
             count_shells(R.nx, R.ny, R.nz, R.nshell, shell_counts);
             for (int a = 0; a < 3; ++a)
                 spec_first[(size_t)a * (nrep + 1) + r + 1] =
-                    spec_first[(size_t)a * (nrep + 1) + r] + fft_tiles(a, R.nx, R.ny, R.nz);
-            spec_first[3 * (size_t)(nrep + 1) + r + 1] =
-                spec_first[3 * (size_t)(nrep + 1) + r] +
-                (uint32_t)((bin_nodes(R.nx, R.ny, R.nz) + kBinPoints - 1) / kBinPoints);
+                    spec_first[(size_t)a * (nrep + 1) + r] + fft_tiles(a, R.nx, R.ny, R.nz, cb);
         }
         ctx->rdev.push_back(R);
-        if (L.sampling) {
-            const uint32_t P = dft_planes_per_block(R.nx);
-            for (uint32_t c = 0; c < (R.nz + P - 1) / P; ++c) chunks.push_back(((uint32_t)r << 16) | c);
-        }
+        if (L.sampling) chunks.push_back(chunks.back() + (uint32_t)dft_chunks(R.nx, R.nz));
     }
     if (L.sampling) {
         hipError_t e = hipMemcpy(ctx->d_chunks(), chunks.data(), sizeof(uint32_t) * chunks.size(),
                                  hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(ctx->d_obs_first(), obs_first.data(), sizeof(uint32_t) * obs_first.size(),
+                          hipMemcpyHostToDevice);
         if (e == hipSuccess && L.spectrum) {
             e = hipMemcpy(ctx->d_scounts(), shell_counts.data(), sizeof(int64_t) * shell_counts.size(),
                           hipMemcpyHostToDevice);
@@ -1022,7 +1061,7 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
     }
     if (hipMemsetAsync(ctx->d_acc(), 0, sizeof(double) * kAccStride * nrep, ctx->stream) != hipSuccess ||
         (L.spectrum &&
-         (hipMemsetAsync(ctx->d_sbins(), 0, sizeof(unsigned long long) * kSpec * L.nshell_total, ctx->stream) !=
+         (hipMemsetAsync(ctx->d_sbins(), 0, sizeof(unsigned long long) * kSpec * kBinCopies * L.nshell_total, ctx->stream) !=
               hipSuccess ||
           hipMemsetAsync(ctx->d_sacc(), 0, sizeof(double) * kSpec * L.nshell_total, ctx->stream) != hipSuccess)) ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
@@ -1174,7 +1213,7 @@ int gmf_reset_stats(gmf_ctx* ctx)
     CK(hipMemsetAsync(ctx->d_acc(), 0, sizeof(double) * kAccStride * ctx->nrep, ctx->stream));
     if (ctx->L.spectrum) {
         CK(hipMemsetAsync(ctx->d_sacc(), 0, sizeof(double) * kSpec * ctx->L.nshell_total, ctx->stream));
-        CK(hipMemsetAsync(ctx->d_sbins(), 0, sizeof(unsigned long long) * kSpec * ctx->L.nshell_total, ctx->stream));
+        CK(hipMemsetAsync(ctx->d_sbins(), 0, sizeof(unsigned long long) * kSpec * kBinCopies * ctx->L.nshell_total, ctx->stream));
     }
     CK(hipStreamSynchronize(ctx->stream));
     return GMF_OK;

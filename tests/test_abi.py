@@ -69,6 +69,10 @@ def test_workspace_bytes_and_validation():
     assert _ws([(14, 10, 8, 1.0, 1.0, 1e-4, 1)], sample_every=5, spectrum=1) == 0  # factor 7
     assert _ws([(2048, 8, 8, 1.0, 1.0, 1e-4, 1)], sample_every=5, spectrum=1) == 0  # longer than 1024
     assert _ws([(12, 10, 8, 1.0, 1.0, 1e-4, 1)], sample_every=5, spectrum=2) == 0
+    # the longest lines along every axis, both precisions (a z line of 1024 FP64 points fills a tile)
+    for box in ((2, 3, 1024), (1024, 6, 5), (3, 1024, 2), (1024, 1024, 2), (1024, 2, 1024)):
+        for prec in (gmf.FP64, gmf.FP32_SHIFTED):
+            assert _ws([box + (1.0, 1.0, 1e-4, 1)], precision=prec, sample_every=5, spectrum=1) > 0, (box, prec)
     # moment storage: two buffers of ten moments instead of 27 populations; GMF
     # collision and the two-buffer scheme only
     mom = _ws([(16, 16, 16, 1.0, 1.0, 1e-4, 1)], storage=gmf.STORE_MOMENTS)
@@ -82,12 +86,12 @@ def test_workspace_bytes_and_validation():
     # fewer than 2^32 nodes in one context (its 32-bit workgroup counts)
     assert _ws([(1024, 1024, 1024, 1.0, 1.0, 1e-4, 1)] * 4, precision=gmf.FP32_SHIFTED) == 0
     assert _ws([(1024, 1024, 1024, 1.0, 1.0, 1e-4, 1)] * 3, precision=gmf.FP32_SHIFTED) > 0
-    # sampling: at most 2^16 DFT chunks per replica, 32-bit offsets of the plane sums
-    assert _ws([(512, 1, 65600, 1.0, 1.0, 1e-4, 1)], precision=gmf.FP32_SHIFTED) > 0
-    assert _ws([(512, 1, 65600, 1.0, 1.0, 1e-4, 1)], precision=gmf.FP32_SHIFTED, sample_every=10) == 0
-    assert _ws([(512, 1, 65536, 1.0, 1.0, 1e-4, 1)], precision=gmf.FP32_SHIFTED, sample_every=10) > 0
+    # sampling: the first DFT stage's partial sums (6 * 28 per plane and block of 64 columns) at 32-bit offsets
+    assert _ws([(512, 1, 65600, 1.0, 1.0, 1e-4, 1)], precision=gmf.FP32_SHIFTED, sample_every=10) > 0
     assert _ws([(1, 1, 1 << 24, 1.0, 1.0, 1e-4, 1)], sample_every=10) > 0
     assert _ws([(1, 1, 1 << 24, 1.0, 1.0, 1e-4, 1)] * 2, sample_every=10) == 0
+    assert _ws([(1, 1, 1 << 25, 1.0, 1.0, 1e-4, 1)]) > 0
+    assert _ws([(1, 1, 1 << 25, 1.0, 1.0, 1e-4, 1)], sample_every=10) == 0
     # the 512^3 stress workload fits both precisions
     assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)]) > 2 * 27 * 8 * 512 ** 3
     assert _ws([(512, 512, 512, 1.0, 0.55, 1e-5, 1)], precision=gmf.FP32_SHIFTED) > 0

@@ -124,12 +124,16 @@ def test_equilibrium_spectra_are_flat():
 
 @pytest.mark.parametrize("box,prec,rtol", [((96, 64, 80), gmf.FP32_SHIFTED, 1e-6), ((60, 72, 50), gmf.FP64, 1e-12),
                                            ((1024, 6, 5), gmf.FP64, 1e-12), ((2, 3, 1024), gmf.FP64, 1e-12),
+                                           ((128, 512, 64), gmf.FP32_SHIFTED, 1e-6),
+                                           ((512, 64, 128), gmf.FP64, 1e-12),
+                                           ((64, 1024, 96), gmf.FP32_SHIFTED, 1e-6),
                                            ((256, 256, 256), gmf.FP32_SHIFTED, 1e-6)])
 def test_full_spectrum_large_boxes(box, prec, rtol):
-    """Mixed-radix lines (96 = 4 4 2 3, 80 = 4 4 5, 60, 72, 50), the longest
-    lines (1024 along x, and along z with two columns per tile), and the 256^3
-    headline box, one sample of the equilibrating fluid 40 steps from rest,
-    against the oracle's FFT of the same state."""
+    """Mixed-radix lines (96 = 16 2 3, 80 = 16 5, 60, 72, 50), the longest
+    lines (1024 along x, y and z), every power-of-two length 64 .. 1024 of the
+    kernels with fixed stages along each axis, and the 256^3 headline box, one
+    sample of the equilibrating fluid 40 steps from rest, against the oracle's
+    FFT of the same state."""
     spec = gmf.ReplicaSpec(*box, 1.0, 0.8, 1e-4, 1)
     say(f"full spectrum {box} prec={prec}")
     with gmf.Context([spec], precision=prec, sample_every=20, spectrum=1) as ctx:
@@ -143,3 +147,35 @@ def test_full_spectrum_large_boxes(box, prec, rtol):
     err = np.max(np.abs(got - ref) / np.max(np.abs(ref), axis=1, keepdims=True))
     say(f"  max rel err {err:.2e}")
     assert err < rtol
+
+
+def test_full_spectrum_bitwise_across_pass_orders_and_batching():
+    """The integer shell sums do not depend on the order of the passes (pass
+    by pass over all fields, or group by group), and a replica's spectra do
+    not depend on the other replicas of its context, also when the replicas'
+    lines go through different kernel classes (64^3: fixed stages; 12 x 10 x 8:
+    stages chosen at run time)."""
+    import os
+    specs = [gmf.ReplicaSpec(64, 64, 64, 1.0, 0.8, 1e-4, 21), gmf.ReplicaSpec(12, 10, 8, 1.0, 0.7, 1e-4, 22)]
+    old = os.environ.get("GMF_FFT_ORDER")
+    res = {}
+    try:
+        for order in ("0", "1"):
+            os.environ["GMF_FFT_ORDER"] = order
+            say(f"full spectrum pass order {order}")
+            with gmf.Context(specs, precision=gmf.FP32_SHIFTED, sample_every=5, spectrum=1) as ctx:
+                ctx.step(20)
+                res[order] = [ctx.spectrum(r)[0] for r in range(2)]
+    finally:
+        if old is None:
+            os.environ.pop("GMF_FFT_ORDER", None)
+        else:
+            os.environ["GMF_FFT_ORDER"] = old
+    for r in range(2):
+        assert np.any(res["0"][r]), r
+        assert np.array_equal(res["0"][r], res["1"][r]), r
+    for r, s in enumerate(specs):
+        say(f"full spectrum single replica {r}")
+        with gmf.Context([s], precision=gmf.FP32_SHIFTED, sample_every=5, spectrum=1) as ctx:
+            ctx.step(20)
+            assert np.array_equal(ctx.spectrum()[0], res["1"][r]), r
