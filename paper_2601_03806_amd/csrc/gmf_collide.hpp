@@ -283,7 +283,7 @@ __device__ __forceinline__ void block_sum_store_nt(double (&v)[NV], double* out)
 constexpr int kObsVals = 2 * kObs + 1;
 template <typename T>
 __device__ __forceinline__ void add_observables(double (&acc)[kObsVals], T rho0, T drho, T jx, T jy, T jz,
-                                                T pdiag, T poff)
+                                                T pdiag, T poff, double w = 1.0)
 {
     const T irho = recip(rho0 + drho);
     double o[kObs];
@@ -297,12 +297,14 @@ __device__ __forceinline__ void add_observables(double (&acc)[kObsVals], T rho0,
     o[7] = (double)(jx * irho);
     o[8] = (double)(jy * irho);
     o[9] = (double)(jz * irho);
+    // w = 0 leaves the record as it is (a node repeated past the box end)
 #pragma unroll
     for (int q = 0; q < kObs; ++q) {
-        acc[2 * q] += o[q];
-        acc[2 * q + 1] = fma(o[q], o[q], acc[2 * q + 1]);
+        const double wo = w * o[q];
+        acc[2 * q] += wo;
+        acc[2 * q + 1] = fma(wo, o[q], acc[2 * q + 1]);
     }
-    acc[2 * kObs] += isfinite(o[0]) ? 0.0 : 1.0;
+    acc[2 * kObs] += isfinite(o[0]) ? 0.0 : w;
 }
 
 template <int NV>

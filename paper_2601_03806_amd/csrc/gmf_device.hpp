@@ -39,7 +39,6 @@ constexpr int kDftPlane = kDftNx * kDftNy;
 constexpr int kShells = 8;
 constexpr int kSpec = 5;
 constexpr int kAccStride = 3 * kObs + kSpec * kShells + 8;  // doubles per replica accumulator
-constexpr int kZSplit = 16;          // z chunks of the third DFT stage
 
 __host__ __device__ constexpr int tcx(int p) { return p / 9 - 1; }
 __host__ __device__ constexpr int tcy(int p) { return (p / 3) % 3 - 1; }

@@ -98,7 +98,7 @@ hipError_t launch_observables(int precision, const RepDev* reps, int32_t nrep, c
 hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, uint32_t max_slices, const double* partials,
                                double* slices, double* acc, double* sample_sq, hipStream_t s);
 hipError_t launch_twiddles(const RepDev* reps, int32_t nrep, double2* tw, hipStream_t s);
-// dft: per replica kFields * nz * dft_col_blocks(nx) * kDftPlane complex; zbuf: nrep * kFields * kZSplit * 196
+// dft: per replica kFields * nz * dft_col_blocks(nx) * kDftPlane complex; zbuf: nrep * kFields * 196
 // complex; first: nrep + 1 prefix sums of the replicas' first-stage workgroups (dft_chunks), nchunks their total
 hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint32_t* first, uint32_t nchunks,
                       const void* fields, const double2* tw, double2* dft, double2* zbuf, double* acc, hipStream_t s);

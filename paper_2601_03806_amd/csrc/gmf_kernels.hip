@@ -348,21 +348,37 @@ __global__ __launch_bounds__(kBlock) void observables_kernel(const RepDev* reps,
 #pragma unroll
     for (int q = 0; q < kObsVals; ++q) acc[q] = 0.0;
     const uint32_t n0 = (blockIdx.x - first[r]) * kObsNodes + threadIdx.x;
-    // batches of four nodes: their 24 loads are issued unconditionally (past
-    // the box end they read the last node again) before any of them is used
-    constexpr int kBatch = 4;
-    for (uint32_t k0 = 0; k0 < kObsNodes / kBlock; k0 += kBatch) {
-        T v[kBatch][kFields];
+    // batches of four nodes, two in flight: a batch's 24 loads are issued
+    // unconditionally (past the box end they read the last node again, which
+    // then adds with weight 0) while the previous batch is being summed
+    constexpr int kBatch = 4, kBatches = kObsNodes / kBlock / kBatch;
+    auto load = [&](T (&v)[kBatch][kFields], int k) {
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const uint32_t n = min(n0 + (k0 + u) * kBlock, R.n - 1);
+            const uint32_t n = min(n0 + (uint32_t)(k * kBatch + u) * kBlock, R.n - 1);
 #pragma unroll
             for (int f = 0; f < kFields; ++f) v[u][f] = fl[(uint64_t)f * N + n];
         }
+    };
+    auto add = [&](T (&v)[kBatch][kFields], int k) {
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u)
-            if (n0 + (k0 + u) * kBlock < R.n)
-                add_observables<T>(acc, rho0, v[u][0], v[u][1], v[u][2], v[u][3], v[u][4], v[u][5]);
+        for (int u = 0; u < kBatch; ++u) {
+            const double w = n0 + (uint32_t)(k * kBatch + u) * kBlock < R.n ? 1.0 : 0.0;
+            add_observables<T>(acc, rho0, v[u][0], v[u][1], v[u][2], v[u][3], v[u][4], v[u][5], w);
+        }
+    };
+    T va[kBatch][kFields], vb[kBatch][kFields];
+    load(va, 0);
+#pragma unroll
+    for (int k = 0; k < kBatches; ++k) {
+        // two register sets in turn (a copy between them would wait for the loads)
+        if (k % 2 == 0) {
+            if (k + 1 < kBatches) load(vb, k + 1);
+            add(va, k);
+        } else {
+            if (k + 1 < kBatches) load(va, k + 1);
+            add(vb, k);
+        }
     }
     block_sum_store<kObsVals>(acc, partials + (size_t)blockIdx.x * kPartialStride);
 }
@@ -526,15 +542,31 @@ __device__ __forceinline__ void dft_plane_body(const RepDev& R, uint32_t chunk, 
         y3r = fma(v, t3.x, y3r);
         y3i = fma(-v, t3.y, y3i);
     };
-    uint32_t y = ylo;
-    for (; y + 8 <= yhi; y += 8) {
-        T v[8];
+    // batches of eight rows, two in flight: the next batch is loaded while one
+    // is summed (past the last whole batch the load repeats it, unused)
+    const uint32_t nfull = (yhi - ylo) / 8;
+    auto load8 = [&](T (&v)[8], uint32_t k) {
+        const uint32_t y0 = ylo + 8 * (k < nfull ? k : nfull - 1);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = col[(uint64_t)(y + u) * nx];
+        for (int u = 0; u < 8; ++u) v[u] = col[(uint64_t)(y0 + u) * nx];
+    };
+    auto add8 = [&](T (&v)[8], uint32_t k) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) add(keep * (double)v[u], y + u);
+        for (int u = 0; u < 8; ++u) add(keep * (double)v[u], ylo + 8 * k + u);
+    };
+    if (nfull > 0) {
+        T va[8], vb[8];
+        load8(va, 0);
+        uint32_t k = 0;
+        for (; k + 1 < nfull; k += 2) {
+            load8(vb, k + 1);
+            add8(va, k);
+            load8(va, k + 2);
+            add8(vb, k + 1);
+        }
+        if (k < nfull) add8(va, k);
     }
-    for (; y < yhi; ++y) add(keep * (double)col[(uint64_t)y * nx], y);
+    for (uint32_t y = ylo + 8 * nfull; y < yhi; ++y) add(keep * (double)col[(uint64_t)y * nx], y);
     Ys[wave][lane][0] = make_double2(y0, 0.0);
     Ys[wave][lane][1] = make_double2(y1r, y1i);
     Ys[wave][lane][2] = make_double2(y2r, y2i);
@@ -616,45 +648,43 @@ __device__ __forceinline__ int shell_of(int n2)
 __device__ constexpr int kShellCount[kShells] = {6, 12, 8, 6, 24, 24, 12, 30};
 constexpr int kDftVec = kDftNx * kDftNy * 7;   // n_x 0..3, n_y -3..3, n_z -3..3
 
-// Stage 2: Z[f][v] = sum_z P[f][z][n_x, n_y] e^{-2 pi i n_z z / nz}, in kZSplit
-// partial sums over contiguous z chunks (blockIdx.z)
+// Stage 2: Z[f][v] = sum_z P[f][z][n_x, n_y] e^{-2 pi i n_z z / nz}, one
+// wavefront per wave vector v (grid.z: groups of four): lane l takes the
+// planes z = l, l + 64, ... (each plane's column-block records summed in
+// block order), and the 64 lane sums are added in a fixed tree order.
 __global__ __launch_bounds__(kBlock) void dft_z_kernel(const RepDev* reps, const double2* __restrict__ tw,
                                                        const double2* __restrict__ dft, double2* zout)
 {
     const RepDev& R = reps[blockIdx.x];
     const int fld = blockIdx.y;
-    const int zs = blockIdx.z;
-    const int v = threadIdx.x;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int v = (int)blockIdx.z * (kBlock / 64) + (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (v >= kDftVec) return;
     const int q = v / (kDftNy * 7);
-    const int sy = (v / 7) % kDftNy - 3;
     const int u = v % 7 - 3;
-    (void)sy;
     const int col = q * kDftNy + ((v / 7) % kDftNy);
     const uint32_t nz = R.nz;
     const double2* twz = tw + R.tw_offset + R.nx + R.ny;
     const uint32_t step = (uint32_t)((u % (int)nz + (int)nz) % (int)nz);
-    const uint32_t per = (nz + kZSplit - 1) / kZSplit;
-    const uint32_t z0 = min(nz, zs * per), z1 = min(nz, z0 + per);
-    uint32_t m = (uint32_t)(((uint64_t)step * z0) % nz);
-    double zr = 0.0, zi = 0.0;
     const uint32_t CB = dft_col_blocks(R.nx);
     const double2* P = dft + R.dft_offset + (uint64_t)fld * nz * CB * kDftPlane + col;
-#pragma unroll 4
-    for (uint32_t z = z0; z < z1; ++z) {
-        // the plane's partial records of its column blocks, in block order
+    double zr = 0.0, zi = 0.0;
+    for (uint32_t z = (uint32_t)lane; z < nz; z += 64u) {
         double2 p = P[(uint64_t)z * CB * kDftPlane];
         for (uint32_t cb = 1; cb < CB; ++cb) {
             const double2 pc = P[((uint64_t)z * CB + cb) * kDftPlane];
             p = make_double2(p.x + pc.x, p.y + pc.y);
         }
-        const double2 t = twz[m];
+        const double2 t = twz[(uint32_t)(((uint64_t)step * z) % nz)];
         zr += p.x * t.x + p.y * t.y;
         zi += p.y * t.x - p.x * t.y;
-        m += step;
-        if (m >= nz) m -= nz;
     }
-    zout[(((size_t)blockIdx.x * kFields + fld) * kZSplit + zs) * kDftVec + v] = make_double2(zr, zi);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        zr += __shfl_xor(zr, off, 64);
+        zi += __shfl_xor(zi, off, 64);
+    }
+    if (lane == 0) zout[((size_t)blockIdx.x * kFields + fld) * kDftVec + v] = make_double2(zr, zi);
 }
 
 // Stage 3: shell averages of the five spectra
@@ -675,13 +705,9 @@ __global__ __launch_bounds__(kBlock) void dft_shell_kernel(const RepDev* reps, c
             double zr[kFields], zi[kFields];
 #pragma unroll
             for (int f = 0; f < kFields; ++f) {
-                zr[f] = 0.0;
-                zi[f] = 0.0;
-                for (int zs = 0; zs < kZSplit; ++zs) {
-                    const double2 zz = zin[(((size_t)blockIdx.x * kFields + f) * kZSplit + zs) * kDftVec + v];
-                    zr[f] += zz.x;
-                    zi[f] += zz.y;
-                }
+                const double2 zz = zin[((size_t)blockIdx.x * kFields + f) * kDftVec + v];
+                zr[f] = zz.x;
+                zi[f] = zz.y;
             }
             const double w = (q > 0 ? 2.0 : 1.0) / (double)R.n;
             auto pow2 = [](double a, double b) { return a * a + b * b; };
@@ -714,7 +740,8 @@ hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uin
         dft_plane_kernel<float><<<grid, kBlock, 0, s>>>(reps, first, nrep, (const float*)fields, tw, dft);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dft_z_kernel<<<dim3(nrep, kFields, kZSplit), kBlock, 0, s>>>(reps, tw, dft, zbuf);
+    dft_z_kernel<<<dim3(nrep, kFields, (kDftVec + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, s>>>(reps, tw, dft,
+                                                                                                  zbuf);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     dft_shell_kernel<<<nrep, kBlock, 0, s>>>(reps, zbuf, acc);

@@ -258,7 +258,7 @@ Layout plan(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         L.dft = take(sizeof(double) * 2 * L.dft_complex);
         L.chunks = take(sizeof(uint32_t) * ((size_t)nrep + 1));   // prefix sums of the first-stage workgroups
         L.twiddles = take(sizeof(double) * 2 * L.tw_complex);
-        L.zbuf = take(sizeof(double) * 2 * kFields * kZSplit * 196 * nrep);
+        L.zbuf = take(sizeof(double) * 2 * kFields * 196 * nrep);
         L.sample_sq = take(sizeof(double) * kObs * nrep);
     }
     L.spectrum = L.sampling && opt->spectrum;
