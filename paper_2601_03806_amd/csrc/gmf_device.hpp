@@ -31,7 +31,7 @@ constexpr int Q = 27;
 constexpr int kBlock = 256;          // threads per workgroup of the lattice kernels
 constexpr int kObs = 10;             // sampled observables (see gmf.h)
 constexpr int kPartialStride = 24;   // doubles per partial record of the observables (2*kObs + 1, padded)
-constexpr uint32_t kObsNodes = 16 * kBlock;   // nodes per workgroup of the observables kernel (16 per thread)
+constexpr uint32_t kObsNodes = 16 * kBlock;   // nodes per workgroup of the observables kernel (FP64 path; 16 per thread)
 constexpr int kFields = 6;           // fields kept for the spectra: drho, jx, jy, jz, pdiag, poff
 constexpr int kDftNx = 4;            // n_x = 0..3 in the first DFT stage
 constexpr int kDftNy = 7;            // n_y = -3..3
@@ -89,8 +89,8 @@ struct RepDev {
     uint32_t row_stride;      // elements between consecutive rows of a group (grp * nx)
     uint32_t tw_offset;       // offset (complex values) of the replica's twiddle tables (nx, ny, nz entries)
     uint32_t slice_first;     // first slice record of the replica in the statistics reduction
-    uint32_t obs_first;       // first workgroup (and partial record) of the replica in observables_kernel
-    uint32_t obs_blocks;      // its workgroups there: ceil(n / kObsNodes)
+    uint32_t obs_first;       // first observables record of the replica (obs_records)
+    uint32_t obs_blocks;      // its records (obs_records)
     uint32_t pad2;
     double rho0;
     double omega;             // 1 / tau
@@ -125,6 +125,14 @@ __host__ __device__ inline uint32_t dft_planes_per_chunk(uint32_t nx) { return n
 __host__ __device__ inline uint64_t dft_chunks(uint32_t nx, uint32_t nz)
 {
     return nx >= kDftCols ? (uint64_t)nz * dft_col_blocks(nx) : ((uint64_t)nz + dft_planes_per_chunk(nx) - 1) / dft_planes_per_chunk(nx);
+}
+
+// Partial observables records of a replica per sample: the FP32 path sums them
+// in the first DFT stage (one record per chunk), the FP64 path in
+// observables_kernel (one per kObsNodes nodes).
+__host__ __device__ inline uint64_t obs_records(bool fp32, uint32_t nx, uint32_t ny, uint32_t nz)
+{
+    return fp32 ? dft_chunks(nx, nz) : ((uint64_t)nx * ny * nz + kObsNodes - 1) / kObsNodes;
 }
 
 // Replica of workgroup b of a grid laid out by the prefix array first

@@ -99,9 +99,11 @@ hipError_t launch_stats_reduce(const RepDev* reps, int32_t nrep, uint32_t max_sl
                                double* slices, double* acc, double* sample_sq, hipStream_t s);
 hipError_t launch_twiddles(const RepDev* reps, int32_t nrep, double2* tw, hipStream_t s);
 // dft: per replica kFields * nz * dft_col_blocks(nx) * kDftPlane complex; zbuf: nrep * kFields * 196
-// complex; first: nrep + 1 prefix sums of the replicas' first-stage workgroups (dft_chunks), nchunks their total
+// complex; first: nrep + 1 prefix sums of the replicas' first-stage workgroups (dft_chunks), nchunks their total;
+// partials: the FP32 path's first stage also writes the observables record of each chunk there
 hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint32_t* first, uint32_t nchunks,
-                      const void* fields, const double2* tw, double2* dft, double2* zbuf, double* acc, hipStream_t s);
+                      const void* fields, const double2* tw, double2* dft, double2* zbuf, double* acc,
+                      double* partials, hipStream_t s);
 // full-box shell spectra of one sample (gmf_fft.hip): first = 3 prefix arrays of
 // nrep + 1 workgroup counts (passes x, y and z with the shell sums), nblk their
 // totals, lds the dynamic LDS bytes of each of the three kernels; spec holds the

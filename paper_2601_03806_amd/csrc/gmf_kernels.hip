@@ -498,38 +498,57 @@ hipError_t launch_twiddles(const RepDev* reps, int32_t nrep, double2* tw, hipStr
 // block).  twx[m] = e^{2 pi i m / nx}, twy[m] = e^{2 pi i m / ny} in memory:
 // the y loop's twiddle indices are uniform, so its twiddles come through
 // scalar loads.
-template <typename T>
-__device__ __forceinline__ void dft_plane_body(const RepDev& R, uint32_t chunk, int fld, const T* __restrict__ fields,
-                                               const double2* __restrict__ twx, const double2* __restrict__ twy,
-                                               double2 (*Ys)[kDftCols][4], double2 (*Tx)[kDftCols], double2* dft)
+// A first-stage chunk as one lane sees it: lane = column (plane z0 + p,
+// x), the y range split over the four wavefronts; a lane without a column
+// reads the chunk's first column (the loads stay unconditional) and adds zero.
+struct DftLane {
+    uint32_t z0, cb, CB, P, lane, wave, ylo, yhi;
+    bool wide;
+    uint64_t off;   // node of the lane's column at y = 0
+    double keep;
+};
+
+__device__ __forceinline__ DftLane dft_lane(const RepDev& R, uint32_t chunk)
 {
+    DftLane g;
     const uint32_t nx = R.nx, ny = R.ny, nz = R.nz;
-    const uint32_t CB = dft_col_blocks(nx), P = dft_planes_per_chunk(nx);
-    const bool wide = nx >= kDftCols;
-    const uint32_t z0 = wide ? chunk / CB : chunk * P;
-    const uint32_t cb = wide ? chunk - z0 * CB : 0u;
+    g.CB = dft_col_blocks(nx);
+    g.P = dft_planes_per_chunk(nx);
+    g.wide = nx >= kDftCols;
+    g.z0 = g.wide ? chunk / g.CB : chunk * g.P;
+    g.cb = g.wide ? chunk - g.z0 * g.CB : 0u;
     // the wavefront index is uniform: the y loop, its twiddle indices and loads stay scalar
-    const uint32_t lane = threadIdx.x & 63u, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // this lane's column: plane z0 + p, x; lanes without a column read the
-    // chunk's first column (the loads stay unconditional) and add zero
-    const uint32_t p = wide ? 0u : lane / nx;
-    const uint32_t x = wide ? cb * kDftCols + lane : lane - p * nx;
-    const bool valid = wide ? x < nx : (p < P && z0 + p < nz);
-    const T* col = fields + R.field_offset + (uint64_t)fld * R.n +
-                   (valid ? (uint64_t)(z0 + p) * nx * ny + x : (uint64_t)z0 * nx * ny + cb * kDftCols);
-    const double keep = valid ? 1.0 : 0.0;
-    // the x twiddles e^{2 pi i q x / nx} (q = 1..3) of the chunk's columns, for
-    // the x-transform below; their loads overlap the y loop
+    g.lane = threadIdx.x & 63u;
+    g.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t p = g.wide ? 0u : g.lane / nx;
+    const uint32_t x = g.wide ? g.cb * kDftCols + g.lane : g.lane - p * nx;
+    const bool valid = g.wide ? x < nx : (p < g.P && g.z0 + p < nz);
+    g.off = valid ? (uint64_t)(g.z0 + p) * nx * ny + x : (uint64_t)g.z0 * nx * ny + g.cb * kDftCols;
+    g.keep = valid ? 1.0 : 0.0;
+    const uint32_t yq = (ny + 3) / 4;
+    g.ylo = min(ny, g.wave * yq);
+    g.yhi = min(ny, g.ylo + yq);
+    return g;
+}
+
+// the x twiddles e^{2 pi i q x / nx} (q = 1..3) of the chunk's columns, for
+// the x-transform; their loads overlap the y loop
+__device__ __forceinline__ void dft_load_tx(const RepDev& R, const DftLane& g, const double2* __restrict__ twx,
+                                            double2 (*Tx)[kDftCols])
+{
+    const uint32_t nx = R.nx;
     if (threadIdx.x < 3 * kDftCols) {
         const uint32_t q = threadIdx.x / kDftCols + 1, c = threadIdx.x % kDftCols;
-        const uint32_t xc = wide ? min(cb * kDftCols + c, nx - 1) : c % nx;
+        const uint32_t xc = g.wide ? min(g.cb * kDftCols + c, nx - 1) : c % nx;
         Tx[q - 1][c] = twx[(uint32_t)(((uint64_t)q * xc) % nx)];
     }
-    // this wavefront's rows
-    const uint32_t yq = (ny + 3) / 4;
-    const uint32_t ylo = min(ny, wave * yq), yhi = min(ny, ylo + yq);
+}
+
+// A lane's y-transform of one field at n_y = 0..3 (twy[m] = e^{2 pi i m / ny}).
+struct YSum {
     double y0 = 0.0, y1r = 0.0, y1i = 0.0, y2r = 0.0, y2i = 0.0, y3r = 0.0, y3i = 0.0;
-    auto add = [&](double v, uint32_t y) {
+    __device__ __forceinline__ void add(double v, uint32_t y, uint32_t ny, const double2* __restrict__ twy)
+    {
         // 2y mod ny and 3y mod ny for y < ny, without loop-carried state
         const uint32_t m2 = 2 * y - (2 * y >= ny ? ny : 0u);
         const uint32_t m3 = 3 * y - ny * ((3 * y >= ny ? 1u : 0u) + (3 * y >= 2 * ny ? 1u : 0u));
@@ -541,10 +560,83 @@ __device__ __forceinline__ void dft_plane_body(const RepDev& R, uint32_t chunk, 
         y2i = fma(-v, t2.y, y2i);
         y3r = fma(v, t3.x, y3r);
         y3i = fma(-v, t3.y, y3i);
-    };
+    }
+};
+
+// The four wavefronts' y sums of one field meet in LDS (in wavefront order);
+// then the x-transform at n_x = 0..3 of each plane's columns in the chunk:
+// the 28 items (n_x, n_y = -3..3, using Y(-n_y) = conj(Y(n_y)) of a real
+// column) of each plane, eight threads per item with a fixed-order shuffle
+// sum, into the partial record of (plane, column block).  Ends with the LDS
+// free again.
+__device__ __forceinline__ void dft_plane_finish(const RepDev& R, const DftLane& g, const YSum& a, int fld,
+                                                 double2 (*Ys)[kDftCols][4], double2 (*Tx)[kDftCols], double2* dft)
+{
+    const uint32_t nx = R.nx, nz = R.nz;
+    Ys[g.wave][g.lane][0] = make_double2(a.y0, 0.0);
+    Ys[g.wave][g.lane][1] = make_double2(a.y1r, a.y1i);
+    Ys[g.wave][g.lane][2] = make_double2(a.y2r, a.y2i);
+    Ys[g.wave][g.lane][3] = make_double2(a.y3r, a.y3i);
+    __syncthreads();
+    {
+        const uint32_t c = threadIdx.x & 63u, k = threadIdx.x >> 6;
+        double2 s = Ys[0][c][k];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) s = make_double2(s.x + Ys[w][c][k].x, s.y + Ys[w][c][k].y);
+        Ys[0][c][k] = s;
+    }
+    __syncthreads();
+    // item it = (plane pp, n_x, n_y); group of eight threads per item
+    const uint32_t grp = threadIdx.x >> 3, sub = threadIdx.x & 7u;
+    const uint32_t nitems = (g.wide ? 1u : g.P) * (uint32_t)kDftPlane;
+    const uint32_t ncols = g.wide ? min(kDftCols, nx - g.cb * kDftCols) : nx;
+    for (uint32_t base = 0; base < nitems; base += kBlock / 8) {
+        const uint32_t it = base + grp;
+        const bool act = it < nitems;
+        const uint32_t pp = act ? it / kDftPlane : 0u, o = act ? it % kDftPlane : 0u;
+        const uint32_t q = o / kDftNy;
+        const int sy = (int)(o % kDftNy) - 3;
+        const uint32_t ay = (uint32_t)(sy < 0 ? -sy : sy);
+        const double sg = sy < 0 ? -1.0 : 1.0;          // conjugate for negative n_y
+        double re = 0.0, im = 0.0;
+        if (act) {
+            for (uint32_t c = sub; c < ncols; c += 8) {
+                const double2 yv = Ys[0][g.wide ? c : pp * nx + c][ay];
+                const double yr = yv.x, yi = sg * yv.y;
+                const double2 t = q == 0 ? make_double2(1.0, 0.0) : Tx[q - 1][c];
+                // (yr + i yi)(c - i s)
+                re += yr * t.x + yi * t.y;
+                im += yi * t.x - yr * t.y;
+            }
+        }
+#pragma unroll
+        for (int off = 4; off > 0; off >>= 1) {
+            re += __shfl_xor(re, off, 64);
+            im += __shfl_xor(im, off, 64);
+        }
+        if (act && sub == 0 && g.z0 + pp < nz)
+            dft[R.dft_offset + (((uint64_t)fld * nz + g.z0 + pp) * g.CB + g.cb) * kDftPlane + o] = make_double2(re, im);
+    }
+    __syncthreads();
+}
+
+// Stage 1, one workgroup per (chunk, field): the y-transform at n_y = 0..3 of
+// the chunk's 64 columns, each thread taking ny / 4 rows of its column in
+// batches of eight, two in flight; then dft_plane_finish.  The y loop's
+// twiddle indices are uniform, so its twiddles come through scalar loads.
+template <typename T>
+__device__ __forceinline__ void dft_plane_body(const RepDev& R, uint32_t chunk, int fld, const T* __restrict__ fields,
+                                               const double2* __restrict__ twx, const double2* __restrict__ twy,
+                                               double2 (*Ys)[kDftCols][4], double2 (*Tx)[kDftCols], double2* dft)
+{
+    const uint32_t nx = R.nx, ny = R.ny;
+    const DftLane g = dft_lane(R, chunk);
+    const T* col = fields + R.field_offset + (uint64_t)fld * R.n + g.off;
+    dft_load_tx(R, g, twx, Tx);
+    YSum a;
     // batches of eight rows, two in flight: the next batch is loaded while one
     // is summed (past the last whole batch the load repeats it, unused)
-    const uint32_t nfull = (yhi - ylo) / 8;
+    const uint32_t ylo = g.ylo, yhi = g.yhi, nfull = (yhi - ylo) / 8;
     auto load8 = [&](T (&v)[8], uint32_t k) {
         const uint32_t y0 = ylo + 8 * (k < nfull ? k : nfull - 1);
 #pragma unroll
@@ -552,7 +644,7 @@ __device__ __forceinline__ void dft_plane_body(const RepDev& R, uint32_t chunk, 
     };
     auto add8 = [&](T (&v)[8], uint32_t k) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) add(keep * (double)v[u], ylo + 8 * k + u);
+        for (int u = 0; u < 8; ++u) a.add(g.keep * (double)v[u], ylo + 8 * k + u, ny, twy);
     };
     if (nfull > 0) {
         T va[8], vb[8];
@@ -566,52 +658,69 @@ __device__ __forceinline__ void dft_plane_body(const RepDev& R, uint32_t chunk, 
         }
         if (k < nfull) add8(va, k);
     }
-    for (uint32_t y = ylo + 8 * nfull; y < yhi; ++y) add(keep * (double)col[(uint64_t)y * nx], y);
-    Ys[wave][lane][0] = make_double2(y0, 0.0);
-    Ys[wave][lane][1] = make_double2(y1r, y1i);
-    Ys[wave][lane][2] = make_double2(y2r, y2i);
-    Ys[wave][lane][3] = make_double2(y3r, y3i);
-    __syncthreads();
-    {
-        // the four wavefronts' sums, in wavefront order, into Ys[0]
-        const uint32_t c = threadIdx.x & 63u, k = threadIdx.x >> 6;
-        double2 s = Ys[0][c][k];
+    for (uint32_t y = ylo + 8 * nfull; y < yhi; ++y) a.add(g.keep * (double)col[(uint64_t)y * nx], y, ny, twy);
+    dft_plane_finish(R, g, a, fld, Ys, Tx, dft);
+}
+
+// Stage 1 with the observables (the FP32 path): one workgroup per chunk and
+// all six fields: each thread reads the six fields of its column's rows
+// (batches of four rows) into the six y-transforms and the observables of each
+// node (weight 0 for a lane without a column), then dft_plane_finish field by
+// field; the observables record of the chunk goes to partials[blockIdx.x].
+template <typename T>
+__device__ __forceinline__ void dft_plane_obs_body(const RepDev& R, uint32_t chunk, const T* __restrict__ fields,
+                                                   const double2* __restrict__ twx, const double2* __restrict__ twy,
+                                                   double2 (*Ys)[kDftCols][4], double2 (*Tx)[kDftCols],
+                                                   double2* dft, double* partials)
+{
+    const uint32_t nx = R.nx, ny = R.ny;
+    const uint64_t N = R.n;
+    const DftLane g = dft_lane(R, chunk);
+    const T* col = fields + R.field_offset + g.off;
+    const T rho0 = rep_param<T>(R.rho0, R.rho0f);
+    dft_load_tx(R, g, twx, Tx);
+    YSum a[kFields];
+    double acc[kObsVals];
 #pragma unroll
-        for (int w = 1; w < 4; ++w) s = make_double2(s.x + Ys[w][c][k].x, s.y + Ys[w][c][k].y);
-        Ys[0][c][k] = s;
-    }
-    __syncthreads();
-    // x-transform: item it = (plane pp, n_x, n_y); group g of eight threads per item
-    const uint32_t g = threadIdx.x >> 3, sub = threadIdx.x & 7u;
-    const uint32_t nitems = (wide ? 1u : P) * (uint32_t)kDftPlane;
-    const uint32_t ncols = wide ? min(kDftCols, nx - cb * kDftCols) : nx;
-    for (uint32_t base = 0; base < nitems; base += kBlock / 8) {
-        const uint32_t it = base + g;
-        const bool act = it < nitems;
-        const uint32_t pp = act ? it / kDftPlane : 0u, o = act ? it % kDftPlane : 0u;
-        const uint32_t q = o / kDftNy;
-        const int sy = (int)(o % kDftNy) - 3;
-        const uint32_t ay = (uint32_t)(sy < 0 ? -sy : sy);
-        const double sg = sy < 0 ? -1.0 : 1.0;          // conjugate for negative n_y
-        double re = 0.0, im = 0.0;
-        if (act) {
-            for (uint32_t c = sub; c < ncols; c += 8) {
-                const double2 yv = Ys[0][wide ? c : pp * nx + c][ay];
-                const double yr = yv.x, yi = sg * yv.y;
-                const double2 t = q == 0 ? make_double2(1.0, 0.0) : Tx[q - 1][c];
-                // (yr + i yi)(c - i s)
-                re += yr * t.x + yi * t.y;
-                im += yi * t.x - yr * t.y;
-            }
-        }
+    for (int q = 0; q < kObsVals; ++q) acc[q] = 0.0;
+    auto add_row = [&](const T (&v)[kFields], uint32_t y) {
 #pragma unroll
-        for (int off = 4; off > 0; off >>= 1) {
-            re += __shfl_xor(re, off, 64);
-            im += __shfl_xor(im, off, 64);
-        }
-        if (act && sub == 0 && z0 + pp < nz)
-            dft[R.dft_offset + (((uint64_t)fld * nz + z0 + pp) * CB + cb) * kDftPlane + o] = make_double2(re, im);
+        for (int f = 0; f < kFields; ++f) a[f].add(g.keep * (double)v[f], y, ny, twy);
+        add_observables<T>(acc, rho0, v[0], v[1], v[2], v[3], v[4], v[5], g.keep);
+    };
+    uint32_t y = g.ylo;
+    for (; y + 4 <= g.yhi; y += 4) {
+        T v[4][kFields];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int f = 0; f < kFields; ++f) v[u][f] = col[(uint64_t)f * N + (uint64_t)(y + u) * nx];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) add_row(v[u], y + u);
     }
+    for (; y < g.yhi; ++y) {
+        T v[kFields];
+#pragma unroll
+        for (int f = 0; f < kFields; ++f) v[f] = col[(uint64_t)f * N + (uint64_t)y * nx];
+        add_row(v, y);
+    }
+#pragma unroll
+    for (int f = 0; f < kFields; ++f) dft_plane_finish(R, g, a[f], f, Ys, Tx, dft);
+    block_sum_store<kObsVals>(acc, partials + (size_t)blockIdx.x * kPartialStride);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dft_plane_obs_kernel(const RepDev* reps, const uint32_t* first,
+                                                               int32_t nrep, const T* __restrict__ fields,
+                                                               const double2* __restrict__ tw, double2* dft,
+                                                               double* partials)
+{
+    __shared__ double2 Ys[4][kDftCols][4];
+    __shared__ double2 Tx[3][kDftCols];
+    const int r = replica_of_block(first, nrep, blockIdx.x);
+    const RepDev R = uniform_rep(reps[r]);
+    const double2* twg = tw + R.tw_offset;            // e^{2 pi i m / nx}, then e^{2 pi i m / ny}
+    dft_plane_obs_body<T>(R, blockIdx.x - first[r], fields, twg, twg + R.nx, Ys, Tx, dft, partials);
 }
 
 template <typename T>
@@ -731,13 +840,15 @@ __global__ __launch_bounds__(kBlock) void dft_shell_kernel(const RepDev* reps, c
 }
 
 hipError_t launch_dft(int precision, const RepDev* reps, int32_t nrep, const uint32_t* first, uint32_t nchunks,
-                      const void* fields, const double2* tw, double2* dft, double2* zbuf, double* acc, hipStream_t s)
+                      const void* fields, const double2* tw, double2* dft, double2* zbuf, double* acc,
+                      double* partials, hipStream_t s)
 {
-    dim3 grid(nchunks, kFields);
     if (precision == kFP64)
-        dft_plane_kernel<double><<<grid, kBlock, 0, s>>>(reps, first, nrep, (const double*)fields, tw, dft);
+        dft_plane_kernel<double><<<dim3(nchunks, kFields), kBlock, 0, s>>>(reps, first, nrep, (const double*)fields,
+                                                                           tw, dft);
     else
-        dft_plane_kernel<float><<<grid, kBlock, 0, s>>>(reps, first, nrep, (const float*)fields, tw, dft);
+        dft_plane_obs_kernel<float><<<nchunks, kBlock, 0, s>>>(reps, first, nrep, (const float*)fields, tw, dft,
+                                                               partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dft_z_kernel<<<dim3(nrep, kFields, (kDftVec + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, s>>>(reps, tw, dft,

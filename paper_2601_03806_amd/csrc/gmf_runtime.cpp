@@ -204,7 +204,7 @@ Layout plan(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         L.total_chunks += (uint32_t)dft_chunks((uint32_t)reps[r].nx, (uint32_t)reps[r].nz);
         L.dft_complex += (uint32_t)(kFields * reps[r].nz * dft_col_blocks((uint32_t)reps[r].nx) * kDftPlane);
         {
-            const uint64_t ob = (n + kObsNodes - 1) / kObsNodes;
+            const uint64_t ob = obs_records(es == 4, reps[r].nx, reps[r].ny, reps[r].nz);
             L.obs_blocks += ob;
             L.obs_slices += (ob + kBlock - 1) / kBlock;
         }
@@ -452,13 +452,16 @@ int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
         CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, step_pattern(ctx, t), ctx->mode, ctx->npt, a,
                        ctx->nblocks, ctx->stream));
     if (sample) {
-        CK(launch_observables(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_obs_first(), ctx->obs_total,
-                              ctx->d_fields(), ctx->d_partials(), ctx->stream));
-        CK(launch_stats_reduce(ctx->d_reps(), ctx->nrep, ctx->max_slices, ctx->d_partials(), ctx->d_slices(),
-                               ctx->d_acc(), ctx->d_sample_sq(), ctx->stream));
+        // the observables records come from observables_kernel (FP64) or from the
+        // first DFT stage (FP32); the statistics reduction follows both
+        if (ctx->opt.precision == GMF_FP64)
+            CK(launch_observables(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_obs_first(), ctx->obs_total,
+                                  ctx->d_fields(), ctx->d_partials(), ctx->stream));
         CK(launch_dft(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_chunks(), ctx->L.total_chunks,
                       ctx->d_fields(), ctx->d_twiddles(), reinterpret_cast<double2*>(ctx->d_dft()), ctx->d_zbuf(),
-                      ctx->d_acc(), ctx->stream));
+                      ctx->d_acc(), ctx->d_partials(), ctx->stream));
+        CK(launch_stats_reduce(ctx->d_reps(), ctx->nrep, ctx->max_slices, ctx->d_partials(), ctx->d_slices(),
+                               ctx->d_acc(), ctx->d_sample_sq(), ctx->stream));
         if (ctx->L.spectrum)
             CK(launch_spectrum(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_sfirst(), ctx->L.spec_blocks,
                                ctx->d_fields(), ctx->d_twiddles(), ctx->d_spec(), ctx->d_sample_sq(),
@@ -985,9 +988,9 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
         R.field_offset = field_off;
         R.dft_offset = dft_off;
         R.tw_offset = tw_off;
-        // observables reduction: workgroups of kObsNodes nodes, slices of kBlock of their records
+        // observables reduction: obs_records partial records, slices of kBlock of them
         R.obs_first = ctx->obs_total;
-        R.obs_blocks = (R.n + kObsNodes - 1) / kObsNodes;
+        R.obs_blocks = (uint32_t)obs_records(opt.precision == GMF_FP32_SHIFTED, R.nx, R.ny, R.nz);
         R.slice_first = slice_off;
         ctx->obs_total += R.obs_blocks;
         slice_off += (R.obs_blocks + kBlock - 1) / kBlock;
