@@ -111,6 +111,78 @@ def time_context(ctx, stream, steps, warmup, torch, loops=None, key=None):
     return e0.elapsed_time(e1) / 1e3   # seconds
 
 
+# launch variants of the step kernels, forced one after the other for the
+# rocprofv3 counter runs (--profile-variants): GMF_ADDRESSING, GMF_BLOCK_MAP,
+# GMF_OCCUPANCY and GMF_MTILE select them (tune 0)
+PROFILE_MAPS = ("linear", "xcd", "xcd16")
+
+
+def profile_variants(args, torch, gmf, wl):
+    """Run every launch variant of one step kernel for 2 + args.steps steps in
+    a fixed order, on the workload that the bench line quotes it for; return
+    the variants as they ran (bench-line key, configuration, kernel launches),
+    so that the step-kernel dispatches of a counter run map onto them in order."""
+    stream = torch.cuda.Stream()
+    kind = args.profile_variants
+    if kind == "ensemble":
+        we = wl.ensemble()
+        specs = [gmf.ReplicaSpec(*bx.n, rho0=bx.rho0, tau=bx.tau, kbt=bx.kbt, seed=bx.seed) for bx in we.boxes]
+        combos = [({"GMF_ADDRESSING": a, "GMF_BLOCK_MAP": m, "GMF_OCCUPANCY": str(k)}, st)
+                  for a in ("1", "3", "27", "plane") for st in (gmf.STREAM_AB, gmf.STREAM_AA)
+                  for m in PROFILE_MAPS for k in (0, 5)]
+        prec, storage = gmf.FP32_SHIFTED, gmf.STORE_POPULATIONS
+    else:
+        b = wl.bandwidth_headline("fp64" if kind == "fp64" else "fp32").boxes[0]
+        specs = [gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed)]
+        if kind == "moments":
+            combos = [({"GMF_MTILE": f"{t},{z}", "GMF_BLOCK_MAP": m}, gmf.STREAM_AB)
+                      for t in range(4) for z in (32, 64, 128) for m in PROFILE_MAPS]
+            prec, storage = gmf.FP32_SHIFTED, gmf.STORE_MOMENTS
+        else:
+            combos = [({"GMF_ADDRESSING": a, "GMF_BLOCK_MAP": m, "GMF_OCCUPANCY": str(k)}, gmf.STREAM_AB)
+                      for a in ("27", "plane") for m in PROFILE_MAPS for k in (0, 5, 4, 3)]
+            prec = gmf.FP64 if kind == "fp64" else gmf.FP32_SHIFTED
+            storage = gmf.STORE_POPULATIONS
+    ran, seen = [], set()
+    for env, st in combos:
+        old = {k: os.environ.get(k) for k in env}
+        os.environ.update(env)
+        try:
+            with gmf.Context(specs, precision=prec, stream=stream, tune=0, storage=storage, streaming=st,
+                             graph_steps=graph_len(args.steps)) as ctx:
+                cfg = ctx.config()
+                key = variant_key(cfg)
+                if key in seen:      # an override that does not fit falls back to a variant already run
+                    continue
+                seen.add(key)
+                time_context(ctx, stream, args.steps, 2, torch)
+                ran.append({"key": key, "config": cfg, "launches": 2 + args.steps})
+                print(f"[bench] variant {key}", file=sys.stderr, flush=True)
+        finally:
+            for k, v in old.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+    torch.cuda.synchronize()
+    return {"profile_variants": kind, "nodes": sum(sp.n for sp in specs), "steps": args.steps, "variants": ran}
+
+
+def profile_sampler(args, torch, gmf, wl):
+    """The headline box sampled every 10 steps with the full-box spectra, the
+    default launch variant (tune 0): the sampler and spectrum kernels for the
+    counter runs."""
+    stream = torch.cuda.Stream()
+    b = wl.bandwidth_headline("fp32").boxes[0]
+    spec = gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed)
+    steps = max(10, args.steps // 10 * 10)
+    with gmf.Context([spec], precision=gmf.FP32_SHIFTED, stream=stream, tune=0, sample_every=10, spectrum=1,
+                     graph_steps=graph_len(steps)) as ctx:
+        sec = time_context(ctx, stream, steps, 10, torch)
+        cfg = ctx.config()
+    return {"profile_sampler": True, "nodes": spec.n, "steps": steps, "seconds": sec, "config": cfg}
+
+
 def run_gpu(args, torch, gmf, wl):
     stream = torch.cuda.Stream()
     out = {}
@@ -469,6 +541,10 @@ def parse_args(argv=None):
                     help="headline run: the 256^3 box, or the 64-replica FP32 ensemble (profiling, with --skip-extra)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain device copy of one population buffer (bandwidth reference)")
+    ap.add_argument("--profile-variants", choices=("fp32", "fp64", "ensemble", "moments"),
+                    help="profiling: run every launch variant of one step kernel in a fixed order (tune 0)")
+    ap.add_argument("--profile-sampler", action="store_true",
+                    help="profiling: the 256^3 box sampled every 10 steps with full-box spectra (tune 0)")
     args = ap.parse_args(argv)
     if args.precision == "fp64" and not args.skip_extra:
         ap.error("--precision fp64 profiles the FP64 kernel alone: add --skip-extra")
@@ -495,6 +571,12 @@ def main():
     gmf.lib()   # fail loudly if the HIP library is missing
     if args.copy_probe:
         print(json.dumps({"copy_probe": copy_probe(torch, gmf)}), flush=True)
+        return
+    if args.profile_variants:
+        print(json.dumps(profile_variants(args, torch, gmf, wl)), flush=True)
+        return
+    if args.profile_sampler:
+        print(json.dumps(profile_sampler(args, torch, gmf, wl)), flush=True)
         return
 
     res = run_gpu(args, torch, gmf, wl)

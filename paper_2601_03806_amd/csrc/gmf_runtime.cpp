@@ -334,7 +334,7 @@ struct gmf_ctx {
     int mtile = kDefaultMTile;     // moment storage: tile shape (index into kMTileX/Y)
     uint32_t mtz = kDefaultMTz;    // moment storage: z planes per tile
     uint32_t xcd_count = 1;        // XCDs of the device
-    int fft_order = 1;             // spectrum passes group by group (1) or pass by pass (0)
+    int fft_order = 0;             // spectrum passes pass by pass (0, measured faster) or group by group (1)
     uint32_t fft_classes[3] = {0, 0, 0};   // per axis: bit c set when a replica's lines are of kernel class c
     int xcd_map = 0;               // workgroup mapping: 0 linear, else an index into kXcdChunks
     uint32_t occ = 0;              // population step: workgroups per CU cap (kOccCap; 0: none)

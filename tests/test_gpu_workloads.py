@@ -255,7 +255,7 @@ def test_gmf_keeps_equilibrium_where_bgk_departs():
 
 
 def test_largest_box_1024cube_aa_with_sampling(tabs):
-    """1024^3 (1.07e9 nodes, 58 GB of populations with the one-buffer AA
+    """1024^3 (1.07e9 nodes, 116 GB of FP32 populations with the one-buffer AA
     pattern), FP32 shifted, sampled every 2 steps: plane-uniform addressing is
     the only one that fits; sampled nodes match the oracle's collision; mass and
     momentum are conserved; the sampler's density variance is positive and
