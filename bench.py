@@ -171,16 +171,17 @@ def profile_variants(args, torch, gmf, wl):
 def profile_sampler(args, torch, gmf, wl):
     """The headline box sampled every 10 steps with the full-box spectra, the
     default launch variant (tune 0): the sampler and spectrum kernels for the
-    counter runs."""
+    counter runs, in the precision of --precision."""
     stream = torch.cuda.Stream()
-    b = wl.bandwidth_headline("fp32").boxes[0]
+    b = wl.bandwidth_headline(args.precision).boxes[0]
     spec = gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed)
     steps = max(10, args.steps // 10 * 10)
-    with gmf.Context([spec], precision=gmf.FP32_SHIFTED, stream=stream, tune=0, sample_every=10, spectrum=1,
+    prec = gmf.FP64 if args.precision == "fp64" else gmf.FP32_SHIFTED
+    with gmf.Context([spec], precision=prec, stream=stream, tune=0, sample_every=10, spectrum=1,
                      graph_steps=graph_len(steps)) as ctx:
         sec = time_context(ctx, stream, steps, 10, torch)
         cfg = ctx.config()
-    return {"profile_sampler": True, "nodes": spec.n, "steps": steps, "seconds": sec, "config": cfg}
+    return {"profile_sampler": True, "precision": args.precision, "nodes": spec.n, "steps": steps, "seconds": sec, "config": cfg}
 
 
 def run_gpu(args, torch, gmf, wl):
@@ -356,6 +357,37 @@ def copy_probe(torch, gmf, gbytes=1.812, reps=20):
     torch.cuda.synchronize()
     sec = e0.elapsed_time(e1) / 1e3 / reps
     return {"bytes_read_plus_written": 2 * 4 * n, "seconds": sec, "gbs": 2 * 4 * n / sec / 1e9}
+
+
+def read_probe(torch, gmf, gbytes=1.812, reps=5):
+    """Read rates of the library's plain read of one 256^3 FP32 population
+    buffer: right after the library's copy has written it (the situation of
+    every spectrum pass, which reads what the pass before it wrote), once more
+    straight after that, and of the copy's source buffer, which was only read
+    before.  The first is the ceiling of kernels that read freshly written
+    data; each figure is the mean over `reps` rounds, HIP events around one
+    launch."""
+    n = (int(gbytes * 1e9) // 16) * 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    names = ("after_write", "again", "read_only_buffer")
+    ms = {k: 0.0 for k in names}
+    for r in range(reps + 1):
+        gmf.copy_probe(a.data_ptr(), b.data_ptr(), 4 * n, s)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        for i, buf in enumerate((b, b, a)):
+            ev[2 * i].record(s)
+            gmf.read_probe(buf.data_ptr(), 4 * n, flag.data_ptr(), s)
+            ev[2 * i + 1].record(s)
+        torch.cuda.synchronize()
+        if r:   # the first round warms up
+            for i, k in enumerate(names):
+                ms[k] += ev[2 * i].elapsed_time(ev[2 * i + 1]) / reps
+    assert int(flag.item()) == 0
+    return {"bytes": 4 * n, **{f"{k}_gbs": round(4 * n / (ms[k] * 1e-3) / 1e9, 1) for k in names}}
 
 
 def cpu_baseline(target_seconds=12.0):
@@ -541,12 +573,14 @@ def parse_args(argv=None):
                     help="headline run: the 256^3 box, or the 64-replica FP32 ensemble (profiling, with --skip-extra)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time a plain device copy of one population buffer (bandwidth reference)")
+    ap.add_argument("--read-probe", action="store_true",
+                    help="only time a plain device read of one population buffer, right after a write and again")
     ap.add_argument("--profile-variants", choices=("fp32", "fp64", "ensemble", "moments"),
                     help="profiling: run every launch variant of one step kernel in a fixed order (tune 0)")
     ap.add_argument("--profile-sampler", action="store_true",
-                    help="profiling: the 256^3 box sampled every 10 steps with full-box spectra (tune 0)")
+                    help="profiling: the 256^3 box sampled every 10 steps with full-box spectra (tune 0; --precision)")
     args = ap.parse_args(argv)
-    if args.precision == "fp64" and not args.skip_extra:
+    if args.precision == "fp64" and not (args.skip_extra or args.profile_sampler):
         ap.error("--precision fp64 profiles the FP64 kernel alone: add --skip-extra")
     if args.workload == "ensemble" and (not args.skip_extra or args.precision != "fp32" or args.storage != "populations"):
         ap.error("--workload ensemble profiles the FP32 population kernel of the ensemble alone: add --skip-extra")
@@ -571,6 +605,9 @@ def main():
     gmf.lib()   # fail loudly if the HIP library is missing
     if args.copy_probe:
         print(json.dumps({"copy_probe": copy_probe(torch, gmf)}), flush=True)
+        return
+    if args.read_probe:
+        print(json.dumps({"read_probe": read_probe(torch, gmf), "copy_probe": copy_probe(torch, gmf)}), flush=True)
         return
     if args.profile_variants:
         print(json.dumps(profile_variants(args, torch, gmf, wl)), flush=True)

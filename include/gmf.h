@@ -338,6 +338,16 @@ int gmf_get_occupancy(gmf_ctx* ctx, int32_t* workgroups_per_cu);
  * ceiling that the step kernel's bandwidth is compared with. */
 int gmf_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream);
 
+/* Read-bandwidth reference: enqueue one plain read of `bytes` (a positive
+ * multiple of 16) from device buffer src (16-byte aligned, caller-owned) on
+ * hip_stream (NULL: the legacy stream).  Asynchronous.  flag is one device
+ * uint32_t (4-byte aligned, caller-owned, not cleared here) that is set to 1
+ * if a value read is not finite, which keeps every load live.  Timed right
+ * after a kernel has written the same buffer, this is the ceiling of the
+ * spectrum passes, each of which reads what the pass before it wrote.
+ * GMF_EINVAL on a NULL pointer, a misaligned pointer or a bad size. */
+int gmf_read_probe(const void* src, size_t bytes, uint32_t* flag, void* hip_stream);
+
 /* Release the context and everything the library allocated for it. */
 void gmf_destroy(gmf_ctx* ctx);
 

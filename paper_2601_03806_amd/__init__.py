@@ -42,8 +42,9 @@ Q = 27
 EXPORTED = (
     "gmf_workspace_bytes", "gmf_init", "gmf_step", "gmf_moments", "gmf_stats", "gmf_reset_stats",
     "gmf_get_populations", "gmf_set_populations", "gmf_get_nodes", "gmf_get_step", "gmf_noise_probe",
-    "gmf_get_config", "gmf_copy_probe", "gmf_destroy", "gmf_strerror", "gmf_spectrum", "gmf_get_tiling",
-    "gmf_get_occupancy", "gmf_prepare", "gmf_get_launch_counts", "gmf_set_reference", "gmf_noise_probe_noalloc",
+    "gmf_get_config", "gmf_copy_probe", "gmf_read_probe", "gmf_destroy", "gmf_strerror", "gmf_spectrum",
+    "gmf_get_tiling", "gmf_get_occupancy", "gmf_prepare", "gmf_get_launch_counts", "gmf_set_reference",
+    "gmf_noise_probe_noalloc",
 )
 PROBE_MAX_NODES = 16384
 
@@ -119,6 +120,8 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(ctypes.c_int32)]
         L.gmf_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.gmf_copy_probe.restype = ctypes.c_int
+        L.gmf_read_probe.argtypes = [vp, ctypes.c_size_t, vp, vp]
+        L.gmf_read_probe.restype = ctypes.c_int
         L.gmf_destroy.argtypes = [vp]
         L.gmf_destroy.restype = None
         L.gmf_strerror.argtypes = [ctypes.c_int]
@@ -209,6 +212,13 @@ def copy_probe(src_ptr: int, dst_ptr: int, nbytes: int, stream=None):
     """Enqueue the library's streaming copy (bandwidth reference) on a torch stream."""
     sp = None if stream is None else int(stream.cuda_stream)
     _check(lib().gmf_copy_probe(src_ptr, dst_ptr, nbytes, sp), "gmf_copy_probe")
+
+
+def read_probe(src_ptr: int, nbytes: int, flag_ptr: int, stream=None):
+    """Enqueue the library's plain read of a device buffer (read-bandwidth reference) on a torch stream;
+    flag_ptr is a device uint32 set to 1 if a value read is not finite."""
+    sp = None if stream is None else int(stream.cuda_stream)
+    _check(lib().gmf_read_probe(src_ptr, nbytes, flag_ptr, sp), "gmf_read_probe")
 
 
 class Context:

@@ -971,4 +971,32 @@ hipError_t launch_spectrum(int precision, const RepDev* reps, int32_t nrep, cons
                                            bins, bin_stride, sacc, max_nshell, lds, classes, order, s);
 }
 
+
+// ---------------------------------------------------------------------------
+// Read-bandwidth reference of the spectrum passes, each of which reads what
+// the kernel before it has just written: one 16-byte load per thread
+// (grid-stride beyond 2^28 threads), summed per thread; a thread whose sum is
+// not finite sets *flag, so the loads are not dead.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void read_probe_kernel(const float4* __restrict__ src, uint64_t n4,
+                                                            uint32_t* flag)
+{
+    float acc = 0.0f;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n4; i += stride) {
+        const float4 v = src[i];
+        acc += (v.x + v.y) + (v.z + v.w);
+    }
+    if (!(fabsf(acc) <= 3.4e38f)) *flag = 1u;
+}
+
+hipError_t launch_read_probe(const void* src, uint64_t bytes, uint32_t* flag, hipStream_t s)
+{
+    const uint64_t n4 = bytes / 16;
+    const uint64_t want = (n4 + kBlock - 1) / kBlock;
+    const uint32_t g = (uint32_t)(want < (1u << 20) ? want : (1u << 20));
+    read_probe_kernel<<<g, kBlock, 0, s>>>(reinterpret_cast<const float4*>(src), n4, flag);
+    return hipGetLastError();
+}
+
 }  // namespace gmf

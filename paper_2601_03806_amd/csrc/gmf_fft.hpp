@@ -308,4 +308,9 @@ __host__ __device__ inline uint32_t box_shells(uint32_t nx, uint32_t ny, uint32_
     return (n2 == 0 ? 0u : shell_of(n2)) + 1u;
 }
 
+
+// Read-bandwidth reference (gmf_read_probe): one plain read of `bytes` (a
+// multiple of 16) from src; *flag is set if a thread's sum is not finite.
+hipError_t launch_read_probe(const void* src, uint64_t bytes, uint32_t* flag, hipStream_t s);
+
 }  // namespace gmf

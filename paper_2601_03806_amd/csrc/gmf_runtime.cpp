@@ -171,8 +171,8 @@ int validate(const gmf_replica* reps, int32_t nrep, const gmf_options* opt)
         }
     }
     if (choose_mode(reps, nrep, es, 1) < 0) return GMF_EINVAL;
-    // sampling: the first DFT stage's work list packs (replica, chunk) into 16
-    // bits each, and the plane sums of all replicas sit at 32-bit offsets
+    // sampling: the first DFT stage's workgroups of all replicas form one
+    // 32-bit grid, and the plane sums of all replicas sit at 32-bit offsets
     if (opt && opt->sample_every > 0) {
         uint64_t dft = 0, chunks = 0;
         for (int r = 0; r < nrep; ++r) {
@@ -1461,6 +1461,14 @@ int gmf_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream)
     if (!src || !dst || bytes == 0 || bytes % 16 != 0 || ((uintptr_t)src % 16) != 0 || ((uintptr_t)dst % 16) != 0)
         return GMF_EINVAL;
     if (launch_copy(src, dst, bytes, static_cast<hipStream_t>(hip_stream)) != hipSuccess) return GMF_EDEVICE;
+    return GMF_OK;
+}
+
+int gmf_read_probe(const void* src, size_t bytes, uint32_t* flag, void* hip_stream)
+{
+    if (!src || !flag || bytes == 0 || bytes % 16 != 0 || ((uintptr_t)src % 16) != 0 || ((uintptr_t)flag % 4) != 0)
+        return GMF_EINVAL;
+    if (launch_read_probe(src, bytes, flag, static_cast<hipStream_t>(hip_stream)) != hipSuccess) return GMF_EDEVICE;
     return GMF_OK;
 }
 

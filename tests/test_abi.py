@@ -124,4 +124,13 @@ def test_init_rejects_before_touching_the_device():
     assert lib.gmf_noise_probe_noalloc(1, 0, 0, 8, 7, None, None, None) == gmf.GMF_EINVAL
     assert lib.gmf_noise_probe_noalloc(1, 0, 0xFFFFFFFF, 2, 0, None, None, None) == gmf.GMF_EINVAL
     assert lib.gmf_noise_probe_noalloc(1, 0, 0, 0, 0, None, None, None) == gmf.GMF_OK
+    # the bandwidth probes check pointers, alignment and size before any device call
+    assert lib.gmf_copy_probe(None, ctypes.c_void_p(256), 16, None) == gmf.GMF_EINVAL
+    assert lib.gmf_copy_probe(ctypes.c_void_p(256), ctypes.c_void_p(512), 24, None) == gmf.GMF_EINVAL
+    assert lib.gmf_read_probe(None, 16, ctypes.c_void_p(256), None) == gmf.GMF_EINVAL
+    assert lib.gmf_read_probe(ctypes.c_void_p(256), 16, None, None) == gmf.GMF_EINVAL
+    assert lib.gmf_read_probe(ctypes.c_void_p(264), 16, ctypes.c_void_p(256), None) == gmf.GMF_EINVAL
+    assert lib.gmf_read_probe(ctypes.c_void_p(256), 0, ctypes.c_void_p(256), None) == gmf.GMF_EINVAL
+    assert lib.gmf_read_probe(ctypes.c_void_p(256), 40, ctypes.c_void_p(256), None) == gmf.GMF_EINVAL
+    assert lib.gmf_read_probe(ctypes.c_void_p(256), 16, ctypes.c_void_p(258), None) == gmf.GMF_EINVAL
     assert gmf.strerror(gmf.GMF_EUNSTABLE).startswith("non-finite")

@@ -247,12 +247,13 @@ def test_moments_and_conservation(w):
         assert np.max(np.abs(u - ou)) < 1e-13
 
 
-@pytest.mark.parametrize("box", [(12, 10, 8), (600, 3, 2), (130, 5, 4)])
+@pytest.mark.parametrize("box", [(12, 10, 8), (600, 3, 2), (130, 5, 4), (20, 130, 6)])
 def test_sampled_statistics_match_oracle(w, box):
     """The fused sampler (observables, spatial variances, shell spectra) equals
     the oracle's brute-force observables of the same states; 600-wide rows take
     the first DFT stage through three passes of columns, 130-wide rows one
-    plane per workgroup in one pass."""
+    plane per workgroup in one pass, and 130 rows in y are 33, 33, 33 and 31
+    rows of the four wavefronts of a first-stage workgroup."""
     spec = gmf.ReplicaSpec(*box, 1.0, 0.6, 1e-4, 5)
     p = oracle_params(spec)
     f = oracle.rest_state(p)
