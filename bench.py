@@ -171,17 +171,18 @@ def profile_variants(args, torch, gmf, wl):
 def profile_sampler(args, torch, gmf, wl):
     """The headline box sampled every 10 steps with the full-box spectra, the
     default launch variant (tune 0): the sampler and spectrum kernels for the
-    counter runs, in the precision of --precision."""
+    counter runs, in the precision of --precision and the storage of --storage."""
     stream = torch.cuda.Stream()
     b = wl.bandwidth_headline(args.precision).boxes[0]
     spec = gmf.ReplicaSpec(*b.n, rho0=b.rho0, tau=b.tau, kbt=b.kbt, seed=b.seed)
     steps = max(10, args.steps // 10 * 10)
     prec = gmf.FP64 if args.precision == "fp64" else gmf.FP32_SHIFTED
-    with gmf.Context([spec], precision=prec, stream=stream, tune=0, sample_every=10, spectrum=1,
+    storage = gmf.STORE_MOMENTS if args.storage == "moments" else gmf.STORE_POPULATIONS
+    with gmf.Context([spec], precision=prec, stream=stream, tune=0, sample_every=10, spectrum=1, storage=storage,
                      graph_steps=graph_len(steps)) as ctx:
         sec = time_context(ctx, stream, steps, 10, torch)
         cfg = ctx.config()
-    return {"profile_sampler": True, "precision": args.precision, "nodes": spec.n, "steps": steps, "seconds": sec, "config": cfg}
+    return {"profile_sampler": True, "precision": args.precision, "storage": args.storage, "nodes": spec.n, "steps": steps, "seconds": sec, "config": cfg}
 
 
 def run_gpu(args, torch, gmf, wl):

@@ -326,6 +326,17 @@ struct gmf_ctx {
     bool own_ws = false;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // the sampling kernels of a sampling step run on a second stream of the
+    // library's own, forked after the step kernel and joined before the next
+    // sampling step writes the fields again (or at the end of gmf_step), so
+    // they overlap the plain steps in between; in the graph step loop they are
+    // a graph of their own (sampler_graph) launched on that stream.  Without
+    // the side stream (population storage, or GMF_SAMPLE_OVERLAP=0) they run
+    // on the main stream, in the step's graph.
+    hipStream_t side = nullptr;
+    hipEvent_t side_fork = nullptr, side_join = nullptr;
+    bool side_open = false;        // sampling work forked and not yet joined
+    hipGraphExec_t sampler_graph = nullptr;
     int npt = kDefaultNpt;
     int grp = 27;                  // storage group size (see gmf_device.hpp)
     int mode = 0;                  // step-kernel addressing mode (choose_mode)
@@ -414,8 +425,11 @@ int build_grid(gmf_ctx* ctx, int npt)
         CK(hipMemcpyAsync(ctx->d_blk2rep(), map.data(), sizeof(uint16_t) * map.size(), hipMemcpyHostToDevice,
                           ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
+    if (ctx->side) CK(hipStreamSynchronize(ctx->side));
     for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
     ctx->graphs.clear();
+    if (ctx->sampler_graph) (void)hipGraphExecDestroy(ctx->sampler_graph);
+    ctx->sampler_graph = nullptr;
     return GMF_OK;
 }
 
@@ -428,6 +442,83 @@ bool sampling_step(const gmf_ctx* ctx, int64_t t)
 // step from the device counter plus offset j.
 int step_pattern(const gmf_ctx* ctx, int64_t t) { return ctx->aa ? ((t & 1) ? kAALocal : kAAPull) : kAB; }
 
+// Order the main stream after the sampling work forked last (no-op if none).
+int join_side(gmf_ctx* ctx)
+{
+    if (ctx->side_open) {
+        CK(hipStreamWaitEvent(ctx->stream, ctx->side_join, 0));
+        ctx->side_open = false;
+    }
+    return GMF_OK;
+}
+
+// The sampling kernels of the sample the step kernel has just written on
+// stream s: observables, the DFT stages of the eight smallest shells, the
+// statistics, and the full-box spectra when they are on.
+int enqueue_sampler(gmf_ctx* ctx, hipStream_t s)
+{
+    // the observables records come from observables_kernel (FP64) or from the
+    // first DFT stage (FP32); the statistics reduction follows both
+    if (ctx->opt.precision == GMF_FP64)
+        CK(launch_observables(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_obs_first(), ctx->obs_total,
+                              ctx->d_fields(), ctx->d_partials(), s));
+    CK(launch_dft(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_chunks(), ctx->L.total_chunks,
+                  ctx->d_fields(), ctx->d_twiddles(), reinterpret_cast<double2*>(ctx->d_dft()), ctx->d_zbuf(),
+                  ctx->d_acc(), ctx->d_partials(), s));
+    CK(launch_stats_reduce(ctx->d_reps(), ctx->nrep, ctx->max_slices, ctx->d_partials(), ctx->d_slices(),
+                           ctx->d_acc(), ctx->d_sample_sq(), s));
+    if (ctx->L.spectrum)
+        CK(launch_spectrum(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_sfirst(), ctx->L.spec_blocks,
+                           ctx->d_fields(), ctx->d_twiddles(), ctx->d_spec(), ctx->d_sample_sq(), ctx->d_scounts(),
+                           ctx->d_sbins(), (uint32_t)(kSpec * ctx->L.nshell_total), ctx->d_sacc(), ctx->L.max_nshell,
+                           ctx->L.spec_lds, ctx->fft_classes, ctx->fft_order, s));
+    return GMF_OK;
+}
+
+// The sampling kernels on the side stream, after the work enqueued so far on
+// the main stream: as the captured sampler graph (graph step loop) or as
+// direct launches.
+int fork_sampler(gmf_ctx* ctx, bool graph)
+{
+    CK(hipEventRecord(ctx->side_fork, ctx->stream));
+    CK(hipStreamWaitEvent(ctx->side, ctx->side_fork, 0));
+    if (graph) {
+        CK(hipGraphLaunch(ctx->sampler_graph, ctx->side));
+    } else {
+        const int rc = enqueue_sampler(ctx, ctx->side);
+        if (rc != GMF_OK) return rc;
+    }
+    CK(hipEventRecord(ctx->side_join, ctx->side));
+    ctx->side_open = true;
+    return GMF_OK;
+}
+
+// Capture the sampler graph on the side stream (once per grid).
+int capture_sampler(gmf_ctx* ctx)
+{
+    if (ctx->sampler_graph) return GMF_OK;
+    hipGraph_t g = nullptr;
+    CK(hipStreamBeginCapture(ctx->side, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_sampler(ctx, ctx->side);
+    hipError_t e = hipStreamEndCapture(ctx->side, &g);
+    if (rc != GMF_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        ctx->poisoned = true;
+        return GMF_EDEVICE;
+    }
+    e = hipGraphInstantiate(&ctx->sampler_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        ctx->sampler_graph = nullptr;
+        ctx->poisoned = true;
+        return GMF_EDEVICE;
+    }
+    return GMF_OK;
+}
+
+// Enqueue the step with index t.  In a graph (in_graph) the kernels read the
+// step from the device counter plus offset j, and a sampling step's kernels
+// on the side stream are left to the caller (run_steps).
 int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
 {
     const int par = ctx->aa ? 0 : (int)(t & 1);
@@ -446,28 +537,19 @@ int enqueue_step(gmf_ctx* ctx, int64_t t, bool in_graph, int j)
     a.tz = ctx->mtz;
     a.occ = ctx->mom ? 0u : ctx->occ;
     const bool sample = sampling_step(ctx, t);
+    // a sampling step writes the fields that the previous sample's kernels read
+    if (sample && !in_graph) {
+        const int rc = join_side(ctx);
+        if (rc != GMF_OK) return rc;
+    }
     if (ctx->mom)
         CK(launch_mstep(ctx->opt.precision, sample, ctx->mtile, a, ctx->nblocks, ctx->stream));
     else
         CK(launch_step(ctx->opt.precision, ctx->opt.collision, sample, step_pattern(ctx, t), ctx->mode, ctx->npt, a,
                        ctx->nblocks, ctx->stream));
     if (sample) {
-        // the observables records come from observables_kernel (FP64) or from the
-        // first DFT stage (FP32); the statistics reduction follows both
-        if (ctx->opt.precision == GMF_FP64)
-            CK(launch_observables(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_obs_first(), ctx->obs_total,
-                                  ctx->d_fields(), ctx->d_partials(), ctx->stream));
-        CK(launch_dft(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_chunks(), ctx->L.total_chunks,
-                      ctx->d_fields(), ctx->d_twiddles(), reinterpret_cast<double2*>(ctx->d_dft()), ctx->d_zbuf(),
-                      ctx->d_acc(), ctx->d_partials(), ctx->stream));
-        CK(launch_stats_reduce(ctx->d_reps(), ctx->nrep, ctx->max_slices, ctx->d_partials(), ctx->d_slices(),
-                               ctx->d_acc(), ctx->d_sample_sq(), ctx->stream));
-        if (ctx->L.spectrum)
-            CK(launch_spectrum(ctx->opt.precision, ctx->d_reps(), ctx->nrep, ctx->d_sfirst(), ctx->L.spec_blocks,
-                               ctx->d_fields(), ctx->d_twiddles(), ctx->d_spec(), ctx->d_sample_sq(),
-                               ctx->d_scounts(), ctx->d_sbins(), (uint32_t)(kSpec * ctx->L.nshell_total), ctx->d_sacc(),
-                               ctx->L.max_nshell, ctx->L.spec_lds, ctx->fft_classes,
-                               ctx->fft_order, ctx->stream));
+        if (!ctx->side) return enqueue_sampler(ctx, ctx->stream);
+        if (!in_graph) return fork_sampler(ctx, false);
     }
     return GMF_OK;
 }
@@ -507,6 +589,10 @@ int capture_graph(gmf_ctx* ctx, int64_t t, int64_t len, hipGraphExec_t* out)
 int find_graph(gmf_ctx* ctx, int64_t t, int64_t len, bool sample, hipGraphExec_t* out)
 {
     const int64_t key = graph_key(t, len, sample);
+    if (sample && ctx->side) {
+        const int rc = capture_sampler(ctx);
+        if (rc != GMF_OK) return rc;
+    }
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         hipGraphExec_t ex;
@@ -531,7 +617,16 @@ int run_steps(gmf_ctx* ctx, int64_t n)
                 CK(launch_set_step(ctx->d_step(), ctx->step, ctx->stream));
                 ctx->dev_step_valid = true;
             }
+            // a sampling step's graph writes the fields the previous sample's kernels read
+            if (sample) {
+                rc = join_side(ctx);
+                if (rc != GMF_OK) return rc;
+            }
             CK(hipGraphLaunch(ex, ctx->stream));
+            if (sample && ctx->side) {
+                rc = fork_sampler(ctx, true);
+                if (rc != GMF_OK) return rc;
+            }
             ctx->step += len;
             n -= len;
             ctx->graph_launches += 1;
@@ -545,7 +640,8 @@ int run_steps(gmf_ctx* ctx, int64_t n)
             ctx->dev_step_valid = false;
         }
     }
-    return GMF_OK;
+    // the caller's stream orders everything gmf_step enqueued
+    return join_side(ctx);
 }
 
 // Capture every graph that run_steps(n) from the current step would launch.
@@ -910,6 +1006,24 @@ int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt_in, v
             return GMF_EDEVICE;
         }
         ctx->own_stream = true;
+    }
+    if (L.sampling) {
+        // the side stream pays where the step kernel leaves HBM bandwidth unused:
+        // moment storage (bound by its vector ALU work) gains 1-2% per sampled
+        // step; the population step streams HBM near the copy rate and loses 2%
+        // when the sampling kernels compete with it.  GMF_SAMPLE_OVERLAP = 0 | 1
+        // forces either.
+        const char* ov = getenv("GMF_SAMPLE_OVERLAP");
+        const bool overlap = ov ? strcmp(ov, "0") != 0 : opt.storage == GMF_STORE_MOMENTS;
+        if (overlap) {
+            if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&ctx->side_fork, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&ctx->side_join, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                gmf_destroy(ctx);
+                return GMF_EDEVICE;
+            }
+        }
     }
 
     // addressing mode (one per context: the step kernel is instantiated for it)
@@ -1477,8 +1591,13 @@ void gmf_destroy(gmf_ctx* ctx)
     if (!ctx) return;
     DeviceGuard g(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
     for (auto& gr : ctx->graphs) (void)hipGraphExecDestroy(gr.second);
+    if (ctx->sampler_graph) (void)hipGraphExecDestroy(ctx->sampler_graph);
     if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->side_fork) (void)hipEventDestroy(ctx->side_fork);
+    if (ctx->side_join) (void)hipEventDestroy(ctx->side_join);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }

@@ -179,3 +179,45 @@ def test_full_spectrum_bitwise_across_pass_orders_and_batching():
         with gmf.Context([s], precision=gmf.FP32_SHIFTED, sample_every=5, spectrum=1) as ctx:
             ctx.step(20)
             assert np.array_equal(ctx.spectrum()[0], res["1"][r]), r
+
+
+@pytest.mark.parametrize("graph_steps,storage", [(0, gmf.STORE_POPULATIONS), (20, gmf.STORE_POPULATIONS),
+                                                 (20, gmf.STORE_MOMENTS)])
+def test_sampling_overlap_is_bitwise(graph_steps, storage):
+    """With a second stream (the default for moment storage, GMF_SAMPLE_OVERLAP=1
+    forces it) the sampling kernels are forked after each sampling step and
+    joined before the next one writes the fields: the statistics and full-box
+    spectra equal those of the same run with everything on one stream
+    (GMF_SAMPLE_OVERLAP=0) bit for bit, through graphs and direct launches,
+    for samples 1, 3 and 10 steps apart (with 10 the runs end six steps after
+    their last sample, so gmf_step's own join is exercised)."""
+    import os
+    specs = [gmf.ReplicaSpec(64, 48, 40, 1.0, 0.8, 1e-4, 31), gmf.ReplicaSpec(20, 18, 16, 1.0, 0.6, 1e-4, 32)]
+    old = os.environ.get("GMF_SAMPLE_OVERLAP")
+    res = {}
+    try:
+        for ov in ("1", "0"):
+            os.environ["GMF_SAMPLE_OVERLAP"] = ov
+            for every in (1, 3, 10):
+                say(f"sampling overlap {ov} every {every} graph_steps {graph_steps} storage {storage}")
+                with gmf.Context(specs, precision=gmf.FP32_SHIFTED, sample_every=every, spectrum=1,
+                                 graph_steps=graph_steps, storage=storage) as ctx:
+                    ctx.step(13)
+                    ctx.step(24)
+                    st = [ctx.stats(r) for r in range(2)]
+                    sp = [ctx.spectrum(r)[0] for r in range(2)]
+                    f = ctx.get_populations(0)
+                res[(ov, every)] = (st, sp, f)
+    finally:
+        if old is None:
+            os.environ.pop("GMF_SAMPLE_OVERLAP", None)
+        else:
+            os.environ["GMF_SAMPLE_OVERLAP"] = old
+    for every in (1, 3, 10):
+        (sa, pa, fa), (sb, pb, fb) = res[("1", every)], res[("0", every)]
+        assert np.array_equal(fa, fb)
+        for r in range(2):
+            assert sa[r]["nsamples"] == sb[r]["nsamples"] > 0
+            for k in ("sum_mean", "sum_meansq", "sum_var", "spectrum"):
+                assert np.array_equal(sa[r][k], sb[r][k]), (every, r, k)
+            assert np.any(pa[r]) and np.array_equal(pa[r], pb[r]), (every, r)
