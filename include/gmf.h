@@ -151,9 +151,11 @@ typedef struct {
                              sampling step or up to graph_steps non-sampling steps
                              (between two samples closer than that, the run from one
                              sample to the next); steps that fit no graph (the tail
-                             of a gmf_step call) are launched directly.  Graphs are
-                             captured on first use or by gmf_prepare; every choice
-                             gives the same bits. */
+                             of a gmf_step call) are launched directly.  With moment
+                             storage a sampling step's sampling kernels are a graph
+                             of their own on the library's second stream (gmf_step).
+                             Graphs are captured on first use or by gmf_prepare;
+                             every choice gives the same bits. */
     int32_t tune;         /* 0: built-in kernel configuration; 1: time the variants at init */
     int32_t streaming;    /* GMF_STREAM_AUTO, GMF_STREAM_AB or GMF_STREAM_AA */
     int32_t spectrum;     /* 1: also accumulate the full-box shell spectra on every
@@ -215,7 +217,12 @@ size_t gmf_workspace_bytes(const gmf_replica* reps, int32_t nrep, const gmf_opti
 int gmf_init(const gmf_replica* reps, int32_t nrep, const gmf_options* opt,
              void* dev_workspace, size_t ws_bytes, void* hip_stream, gmf_ctx** out);
 
-/* Enqueue n >= 0 steps of Eq. (10) (or Eq. (1)) on every replica.  Asynchronous. */
+/* Enqueue n >= 0 steps of Eq. (10) (or Eq. (1)) on every replica.  Asynchronous.
+ * Everything is ordered on the context's stream when the call returns.  With
+ * moment storage the sampling kernels of each sampling step run on a second
+ * stream of the library's own, which waits for the step and which the
+ * context's stream waits for before the next sampling step and before this
+ * call returns; the results are the same bits as on one stream. */
 int gmf_step(gmf_ctx* ctx, int64_t n);
 
 /* Capture (without running anything) every HIP graph that gmf_step(ctx, n)
