@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmf.so")
-SOURCES = ["gmf_kernels.hip", "gmf_mstep.hip", "gmf_fft.hip", "gmf_runtime.cpp"]
+SOURCES = ["gmf_kernels.hip", "gmf_sample.hip", "gmf_mstep.hip", "gmf_fft.hip", "gmf_runtime.cpp"]
 ARCH = os.environ.get("GMF_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept out of the generated code on purpose.
