@@ -284,6 +284,45 @@ def test_sampled_statistics_match_oracle(w, box):
     np.testing.assert_allclose(st["spectrum"], exp_spec, rtol=1e-9, atol=1e-20)
 
 
+@pytest.mark.parametrize("storage", [gmf.STORE_POPULATIONS, gmf.STORE_MOMENTS])
+@pytest.mark.parametrize("box", [(70, 130, 9), (12, 10, 8)])
+def test_sampled_statistics_fp32_match_oracle_observables(w, box, storage):
+    """The FP32 sampler (the first DFT stage with the observables in one
+    kernel, then the z stage, the shell sums and the statistics) against the
+    oracle's brute-force observables of the very states it sampled (read back
+    as FP64 before each sampling step): they differ only by the FP32 moments
+    the sampling step forms (about 1e-7 of each field), so variances, mean
+    squares and the eight-shell spectra agree to 1e-5 relative.  70 x 130 rows
+    take two column blocks of 64, one partly empty, and 130 rows split 33, 33,
+    33, 31 over the four wavefronts; 12 x 10 x 8 puts five planes in one
+    workgroup; moment storage forms the fields from the ten stored moments."""
+    spec = gmf.ReplicaSpec(*box, 1.0, 0.6, 1e-4, 9)
+    p = oracle_params(spec)
+    N = spec.n
+    exp_mean = np.zeros(10)
+    exp_msq = np.zeros(10)
+    exp_var = np.zeros(10)
+    exp_spec = np.zeros((5, 8))
+    say(f"FP32 sampler vs oracle observables {box} storage {storage}")
+    with gmf.Context([spec], precision=gmf.FP32_SHIFTED, sample_every=25, storage=storage) as ctx:
+        for t in (0, 25, 50, 75, 100):
+            assert ctx.t == t
+            sums, spec_o = oracle.observables(p, ctx.get_populations())
+            m, m2 = sums[:, 0] / N, sums[:, 1] / N
+            exp_mean += m
+            exp_msq += m2
+            exp_var += m2 - m * m
+            exp_spec += spec_o
+            ctx.step(25 if t < 100 else 1)
+        st = ctx.stats()
+    assert st["nsamples"] == 5
+    np.testing.assert_allclose(st["sum_var"], exp_var, rtol=1e-5, atol=1e-20)
+    np.testing.assert_allclose(st["sum_meansq"], exp_msq, rtol=1e-5, atol=1e-20)
+    # spatial means of conserved quantities are roundoff-sized: absolute tolerance
+    np.testing.assert_allclose(st["sum_mean"], exp_mean, rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(st["spectrum"], exp_spec, rtol=1e-5, atol=1e-20)
+
+
 def test_error_paths_on_device():
     import ctypes
     spec = gmf.ReplicaSpec(8, 8, 8, 1.0, 0.8, 1e-4, 1)
