@@ -254,8 +254,9 @@ def run_gpu(args, torch, gmf, wl):
             sec = time_context(ctx, stream, sa, args.warmup, torch, loops, "aa")
             out["aa"] = {"seconds": sec, "nodes": spec.n, "steps": sa, "config": ctx.config()}
         torch.cuda.synchronize()
-        # the headline box with the fused sampler on (every 10 steps: variances and shell spectra)
-        ss = max(20, args.steps // 4) // 10 * 10
+        # the headline box with the fused sampler on (every 10 steps: variances and shell spectra);
+        # at least 100 timed steps (10 samples), so that a sample's cost is averaged over several
+        ss = max(100, args.steps // 4) // 10 * 10
         with gmf.Context([spec], precision=gmf.FP32_SHIFTED, stream=stream, tune=args.tune,
                          sample_every=10, graph_steps=graph_len(ss)) as ctx:
             print(f"[bench] fp32 sampled every 10: steps {ss}", file=sys.stderr, flush=True)
